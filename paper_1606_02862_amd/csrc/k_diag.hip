@@ -1,0 +1,257 @@
+// FP64 diagnostics: field and kinetic energies, node charge density, the
+// Gauss residual G = div E - rho against its reference, div B, and a count of
+// non-finite field entries.  Two-pass reductions: each workgroup writes its
+// partial sum / maximum, then one workgroup combines the partials in a fixed
+// order, so the results do not depend on scheduling.
+#include "pic_device.hpp"
+
+namespace pic {
+
+constexpr int RED_BLOCKS = 1024;
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum (is_max = false) or maximum over the 256 lanes; result valid in lane 0.
+__device__ inline double block_reduce(double v, bool is_max, double* scratch)
+{
+    v = is_max ? wave_max(v) : wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = scratch[0];
+        for (int w = 1; w < BLOCK / 64; ++w) r = is_max ? fmax(r, scratch[w]) : r + scratch[w];
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_field_energy(GridView g, double* partial)
+{
+    __shared__ double scratch[BLOCK / 64];
+    const int64_t N3 = 3LL * g.nx * g.ny * g.nz;
+    double se = 0.0, sb = 0.0, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < N3; i += (int64_t)gridDim.x * BLOCK) {
+        const double e = g.E[i], b = g.B[i];
+        if (!isfinite(e) || !isfinite(b)) bad += 1.0;
+        else { se += e * e; sb += b * b; }
+    }
+    se = block_reduce(se, false, scratch);
+    sb = block_reduce(sb, false, scratch);
+    bad = block_reduce(bad, false, scratch);
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x + 0] = se;
+        partial[3 * blockIdx.x + 1] = sb;
+        partial[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+// Combine nb partials of `stride` values each; value v goes to result[dst[v]]
+// scaled by scale[v], as a sum or (op bit v set) a maximum.
+struct Finalize {
+    int nb, stride, nvals;
+    int dst[4];
+    double scale[4];
+    unsigned max_mask;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_finalize(const double* partial, Finalize f, double* result)
+{
+    __shared__ double scratch[BLOCK / 64];
+    for (int v = 0; v < f.nvals; ++v) {
+        const bool mx = (f.max_mask >> v) & 1u;
+        double a = 0.0;
+        for (int b = threadIdx.x; b < f.nb; b += BLOCK) {
+            const double x = partial[(int64_t)b * f.stride + v];
+            a = mx ? fmax(a, x) : a + x;
+        }
+        a = block_reduce(a, mx, scratch);
+        if (threadIdx.x == 0) result[f.dst[v]] = a * f.scale[v];
+    }
+}
+
+hipError_t launch_field_energy(const GridView& g, const DiagBuffers& d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_field_energy, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.partial);
+    Finalize f{};
+    f.nb = RED_BLOCKS;
+    f.stride = 3;
+    f.nvals = 3;
+    const double dV = (double)g.dx * g.dy * g.dz;
+    f.dst[0] = D_WE; f.scale[0] = 0.5 * dV;
+    f.dst[1] = D_WB; f.scale[1] = 0.5 * dV;
+    f.dst[2] = D_NONFINITE; f.scale[2] = 1.0;
+    f.max_mask = 0;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, d.partial, f, d.result);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- kinetic
+__global__ __launch_bounds__(BLOCK) void k_kinetic(GridView g, SpeciesView s, double* partial)
+{
+    __shared__ double scratch[BLOCK / 64];
+    const int sc = blockIdx.x;
+    const int n = s.count[sc];
+    const int64_t base = (int64_t)sc * s.cap;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < n; t += BLOCK) {
+        const double ux = s.ux[base + t], uy = s.uy[base + t], uz = s.uz[base + t];
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        acc += (double)s.w[base + t] * (u2 / (1.0 + sqrt(1.0 + u2)));  // gamma - 1
+    }
+    acc = block_reduce(acc, false, scratch);
+    if (threadIdx.x == 0) partial[sc] = acc * (double)s.mass;
+}
+
+hipError_t launch_kinetic(const GridView& g, const SpeciesView& s, const DiagBuffers& d, int slot, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kinetic, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, d.partial);
+    Finalize f{};
+    f.nb = g.nsc;
+    f.stride = 1;
+    f.nvals = 1;
+    f.dst[0] = D_KIN0 + slot;
+    f.scale[0] = 1.0;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, d.partial, f, d.result);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- rho
+template <int ORDER>
+__device__ inline void rho_weights(double x, int* first, double* w)
+{
+    if constexpr (ORDER == 1) {
+        const double f = floor(x), d = x - f;
+        *first = (int)f;
+        w[0] = 1.0 - d;
+        w[1] = d;
+        w[2] = 0.0;
+    } else {
+        const double r = floor(x + 0.5), d = x - r;
+        *first = (int)r - 1;
+        w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+        w[1] = 0.75 - d * d;
+        w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    }
+}
+
+template <int ORDER>
+__global__ __launch_bounds__(BLOCK) void k_rho(GridView g, SpeciesView s, double* rho)
+{
+    const int sc = blockIdx.x;
+    const int n = s.count[sc];
+    const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
+    const int64_t base = (int64_t)sc * s.cap;
+    const double inv_dv = 1.0 / ((double)g.dx * g.dy * g.dz);
+    for (int t = threadIdx.x; t < n; t += BLOCK) {
+        const int64_t p = base + t;
+        double q = s.charge;
+        if (s.zs) q *= (double)s.zs[p];
+        const double qw = q * (double)s.w[p] * inv_dv;
+        int fx, fy, fz;
+        double wx[3], wy[3], wz[3];
+        rho_weights<ORDER>((double)s.x[p], &fx, wx);
+        rho_weights<ORDER>((double)s.y[p], &fy, wy);
+        rho_weights<ORDER>((double)s.z[p], &fz, wz);
+        for (int c = 0; c <= ORDER; ++c) {
+            int gz = scz * SZ + fz + c;
+            gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
+            for (int b = 0; b <= ORDER; ++b) {
+                int gy = scy * SY + fy + b;
+                gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
+                for (int a = 0; a <= ORDER; ++a) {
+                    int gx = scx * SX + fx + a;
+                    gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
+                    unsafeAtomicAdd(&rho[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz)], qw * wx[a] * wy[b] * wz[c]);
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_rho_deposit(const GridView& g, const SpeciesView& s, int order, double* rho, hipStream_t st)
+{
+    if (order == 1) hipLaunchKernelGGL(k_rho<1>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    else hipLaunchKernelGGL(k_rho<2>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Gauss
+// mode 0: store G = div E - rho as the reference; mode 1: reduce
+// max |G - G0|, max |rho|, sum rho dV and max |div B| (at cell centres).
+__global__ __launch_bounds__(BLOCK) void k_gauss(GridView g, const double* rho, double* g0, double rho_bg, int mode,
+                                                 double* partial)
+{
+    __shared__ double scratch[BLOCK / 64];
+    const int N = g.nx * g.ny * g.nz;
+    const double idx = 1.0 / (double)g.dx, idy = 1.0 / (double)g.dy, idz = 1.0 / (double)g.dz;
+    double gmax = 0.0, rmax = 0.0, rsum = 0.0, bmax = 0.0;
+    for (int c = blockIdx.x * BLOCK + threadIdx.x; c < N; c += gridDim.x * BLOCK) {
+        const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+        const int im = (i == 0) ? c + g.nx - 1 : c - 1;
+        const int jm = (j == 0) ? c + (g.ny - 1) * g.nx : c - g.nx;
+        const int km = (k == 0) ? c + (g.nz - 1) * g.nx * g.ny : c - g.nx * g.ny;
+        const int ip = (i + 1 == g.nx) ? c - i : c + 1;
+        const int jp = (j + 1 == g.ny) ? c - j * g.nx : c + g.nx;
+        const int kp = (k + 1 == g.nz) ? c - k * g.nx * g.ny : c + g.nx * g.ny;
+        const double divE = ((double)g.E[c] - (double)g.E[im]) * idx +
+                            ((double)g.E[N + c] - (double)g.E[N + jm]) * idy +
+                            ((double)g.E[2 * N + c] - (double)g.E[2 * N + km]) * idz;
+        const double r = rho[c] + rho_bg;
+        const double G = divE - r;
+        if (mode == 0) {
+            g0[c] = G;
+        } else {
+            const double divB = ((double)g.B[ip] - (double)g.B[c]) * idx +
+                                ((double)g.B[N + jp] - (double)g.B[N + c]) * idy +
+                                ((double)g.B[2 * N + kp] - (double)g.B[2 * N + c]) * idz;
+            gmax = fmax(gmax, fabs(G - g0[c]));
+            rmax = fmax(rmax, fabs(r));
+            rsum += r;
+            bmax = fmax(bmax, fabs(divB));
+        }
+    }
+    if (mode == 0) return;
+    gmax = block_reduce(gmax, true, scratch);
+    rmax = block_reduce(rmax, true, scratch);
+    rsum = block_reduce(rsum, false, scratch);
+    bmax = block_reduce(bmax, true, scratch);
+    if (threadIdx.x == 0) {
+        partial[4 * blockIdx.x + 0] = gmax;
+        partial[4 * blockIdx.x + 1] = rmax;
+        partial[4 * blockIdx.x + 2] = rsum;
+        partial[4 * blockIdx.x + 3] = bmax;
+    }
+}
+
+hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gauss, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.rho, d.g0, rho_bg, mode, d.partial);
+    if (mode == 0) return hipGetLastError();
+    Finalize f{};
+    f.nb = RED_BLOCKS;
+    f.stride = 4;
+    f.nvals = 4;
+    f.dst[0] = D_GAUSS; f.scale[0] = 1.0;
+    f.dst[1] = D_RHOMAX; f.scale[1] = 1.0;
+    f.dst[2] = D_CHARGE; f.scale[2] = (double)g.dx * g.dy * g.dz;
+    f.dst[3] = D_DIVB; f.scale[3] = 1.0;
+    f.max_mask = 0b1011;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, d.partial, f, d.result);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,68 @@
+// Yee FDTD updates on the periodic staggered grid (Yee 1966), one lane per
+// cell, x fastest so every component row is read and written coalesced:
+//   B -= coef * curl E   (forward differences of E, at the B locations)
+//   E += coef * (curl B - J)   (backward differences of B, at the E locations)
+// The PIC cycle applies B(dt/2), E(dt), B(dt/2).
+#include "pic_device.hpp"
+
+namespace pic {
+
+__global__ __launch_bounds__(BLOCK) void k_yee_b(GridView g, float cx, float cy, float cz)
+{
+    const int N = g.nx * g.ny * g.nz;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= N) return;
+    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    const int ip = (i + 1 == g.nx) ? c - i : c + 1;
+    const int jp = (j + 1 == g.ny) ? c - j * g.nx : c + g.nx;
+    const int kp = (k + 1 == g.nz) ? c - k * g.nx * g.ny : c + g.nx * g.ny;
+    const float* Ex = g.E;
+    const float* Ey = g.E + N;
+    const float* Ez = g.E + 2 * N;
+    const float ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    const float curl_x = cy * (Ez[jp] - ez) - cz * (Ey[kp] - ey);
+    const float curl_y = cz * (Ex[kp] - ex) - cx * (Ez[ip] - ez);
+    const float curl_z = cx * (Ey[ip] - ey) - cy * (Ex[jp] - ex);
+    g.B[c] -= curl_x;
+    g.B[N + c] -= curl_y;
+    g.B[2 * N + c] -= curl_z;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_yee_e(GridView g, float cx, float cy, float cz, float coef)
+{
+    const int N = g.nx * g.ny * g.nz;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= N) return;
+    const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+    const int im = (i == 0) ? c + g.nx - 1 : c - 1;
+    const int jm = (j == 0) ? c + (g.ny - 1) * g.nx : c - g.nx;
+    const int km = (k == 0) ? c + (g.nz - 1) * g.nx * g.ny : c - g.nx * g.ny;
+    const float* Bx = g.B;
+    const float* By = g.B + N;
+    const float* Bz = g.B + 2 * N;
+    const float bx = Bx[c], by = By[c], bz = Bz[c];
+    const float curl_x = cy * (bz - Bz[jm]) - cz * (by - By[km]);
+    const float curl_y = cz * (bx - Bx[km]) - cx * (bz - Bz[im]);
+    const float curl_z = cx * (by - By[im]) - cy * (bx - Bx[jm]);
+    g.E[c] += curl_x - coef * g.J[c];
+    g.E[N + c] += curl_y - coef * g.J[N + c];
+    g.E[2 * N + c] += curl_z - coef * g.J[2 * N + c];
+}
+
+hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st)
+{
+    const int N = g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_yee_b, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, coef / g.dx, coef / g.dy,
+                       coef / g.dz);
+    return hipGetLastError();
+}
+
+hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st)
+{
+    const int N = g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_yee_e, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, coef / g.dx, coef / g.dy,
+                       coef / g.dz, coef);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,68 @@
+// Device-side helpers shared by the kernels: the Philox4x64-10 generator and
+// the CIC / TSC assignment weights.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic_internal.hpp"
+
+namespace pic {
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw; "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): ten rounds, each two 64x64 -> 128-bit products of
+// counter words with fixed multipliers, xor-mixed with a key that advances by
+// the Weyl constants between rounds.
+struct Philox4 {
+    uint64_t v[4];
+};
+
+__device__ inline Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+// Uniform double in (0,1) from the top 53 bits of a word.
+__device__ inline double u01(uint64_t w)
+{
+    return ((double)(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// Counter layout: (particle id, species, purpose, step), key (seed, 0).
+enum Purpose { PURPOSE_POSITION = 0, PURPOSE_MOMENTUM = 1, PURPOSE_IONIZE = 2 };
+
+// ---------------------------------------------------------------- shapes
+// CIC: nodes f, f+1 with f = floor(x); weights 1-d, d (d = x - f).
+// TSC: nodes r-1, r, r+1 with r = floor(x + 1/2); d = x - r in [-1/2, 1/2):
+//      1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2.
+template <int ORDER>
+__device__ inline int shape_weights(float x, float* w)
+{
+    if constexpr (ORDER == 1) {
+        const float f = floorf(x);
+        const float d = x - f;
+        w[0] = 1.0f - d;
+        w[1] = d;
+        return (int)f;
+    } else {
+        const float r = floorf(x + 0.5f);
+        const float d = x - r;
+        const float a = 0.5f - d, b = 0.5f + d;
+        w[0] = 0.5f * a * a;
+        w[1] = 0.75f - d * d;
+        w[2] = 0.5f * b * b;
+        return (int)r - 1;
+    }
+}
+
+}  // namespace pic

@@ -1,0 +1,110 @@
+// Internal structures of the gfx950 particle-in-cell library: device views
+// passed to kernels by value, and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+// Supercell: 8 x 8 x 4 = 256 cells, one 256-lane workgroup (4 wave64) each,
+// as in the paper's block-per-supercell mapping.  A frame is 256 slots.
+constexpr int SX = PIC_SUPERCELL_X, SY = PIC_SUPERCELL_Y, SZ = PIC_SUPERCELL_Z;
+constexpr int SC_CELLS = SX * SY * SZ;
+constexpr int BLOCK = 256;
+constexpr int MAX_MIGRATE = 4096;  // per supercell, per species, per step
+
+// Largest float below a power of two s (the far face of a supercell).
+__host__ __device__ constexpr float below(float s) { return s - s * 0x1p-24f; }
+constexpr float XMAX = below((float)SX), YMAX = below((float)SY), ZMAX = below((float)SZ);
+
+// Device error flags (int32 each).
+enum Flag { FLAG_CAPACITY = 0, FLAG_MIGRATE = 1, FLAG_CFL = 2, FLAG_NONFINITE = 3, NFLAGS = 4 };
+
+struct GridView {
+    int nx, ny, nz;        // cells
+    int ncx, ncy, ncz;     // supercells per axis
+    int nsc;               // number of supercells
+    int xcd_remap;         // 1: map blockIdx so each XCD gets a contiguous slab
+    float dx, dy, dz, dt;
+    float b0x, b0y, b0z;
+    float* E;              // 3 * N, component-major, x fastest
+    float* B;
+    float* J;
+    int32_t* flags;
+};
+
+struct SpeciesView {
+    float *x, *y, *z;       // supercell-relative positions in cells: [0,8)x[0,8)x[0,4)
+    float *ux, *uy, *uz;    // u = gamma v
+    float* w;               // macro weight
+    uint32_t* id;
+    uint8_t* zs;            // charge state, or nullptr
+    int32_t* count;         // particles per supercell
+    int cap;                // slots per supercell (multiple of 256)
+    // migration buffers: per destination supercell, cap_in slots
+    float *ix, *iy, *iz, *iux, *iuy, *iuz, *iw;
+    uint32_t* iid;
+    uint8_t* izs;
+    int32_t* in_count;      // arrivals per supercell
+    int32_t* holes;         // per source supercell: vacated slots
+    int32_t* hole_count;
+    int cap_in;
+    float charge;           // in e (per unit Z when zs != nullptr)
+    float mass;
+};
+
+struct Species {
+    SpeciesView v;
+    pic_species_t desc;
+    int64_t n_init;        // particles at t = 0
+    int64_t id_offset;     // first id at t = 0
+    double weight;
+};
+
+// Map a workgroup index to a supercell so that the 8 XCDs (which receive
+// workgroups round-robin) each work on one contiguous slab of supercells and
+// share its guard cells in their own L2.
+__host__ __device__ inline int sc_of_block(int b, int nsc, int remap)
+{
+    if (!remap) return b;
+    const int per = nsc >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init_species(const GridView& g, const SpeciesView& s, uint64_t seed, int species_index,
+                               int ppc, int64_t id_offset, int pos_index, int pos_ppc, int64_t pos_id_offset,
+                               float u_th, const float drift_u[3], int layout, float weight, int z_init,
+                               hipStream_t st);
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, hipStream_t st);
+hipError_t launch_migrate(const GridView& g, const SpeciesView& s, hipStream_t st);
+hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st);
+hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st);
+
+// FP64 diagnostics.  partial buffers hold one entry per workgroup.
+struct DiagBuffers {
+    double* rho;       // N
+    double* g0;        // N, Gauss reference
+    double* partial;   // scratch for block partial sums / maxima
+    int npartial;
+    double* result;    // small device result vector
+};
+hipError_t launch_field_energy(const GridView& g, const DiagBuffers& d, hipStream_t st);
+hipError_t launch_kinetic(const GridView& g, const SpeciesView& s, const DiagBuffers& d, int slot, hipStream_t st);
+hipError_t launch_rho_deposit(const GridView& g, const SpeciesView& s, int order, double* rho, hipStream_t st);
+hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st);
+
+// Result vector layout of the diagnostics.
+enum DiagSlot {
+    D_WE = 0, D_WB = 1, D_NONFINITE = 2, D_CHARGE = 3, D_RHOMAX = 4, D_GAUSS = 5, D_DIVB = 6,
+    D_KIN0 = 8,  // + species index
+    D_NSLOTS = 16
+};
+
+}  // namespace pic

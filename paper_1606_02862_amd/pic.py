@@ -1,0 +1,189 @@
+"""Python handle over the C ABI: marshals workload dictionaries into the C
+structs, supplies device memory from PyTorch's caching allocator and the
+current HIP stream, and copies state in and out as numpy arrays.  Every
+step of the simulation runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _capi as A
+
+_LAYOUT = {"uniform": 0, "shear": 1, "beams": 2}
+_SHAPE = {"cic": 1, "tsc": 2}
+
+
+def grid_struct(cfg: dict) -> A.GridT:
+    gc = cfg["grid"]
+    g = A.GridT()
+    g.nx, g.ny, g.nz = gc["nx"], gc["ny"], gc["nz"]
+    g.dx, g.dy, g.dz, g.dt = gc["dx"], gc["dy"], gc["dz"], gc["dt"]
+    g.b0[:] = list(gc["b0"])
+    g.rho_bg = gc["rho_bg"]
+    g.seed = gc["seed"]
+    g.n_ref_cm3 = gc.get("n_ref_cm3", 1e21)
+    return g
+
+
+def species_structs(cfg: dict):
+    sps = cfg["species"]
+    arr = (A.SpeciesT * len(sps))()
+    for i, sp in enumerate(sps):
+        s = arr[i]
+        s.charge, s.mass, s.density, s.u_th = sp["charge"], sp["mass"], sp["density"], sp["u_th"]
+        s.drift_beta[:] = list(sp["drift_beta"])
+        s.ppc = sp["ppc"]
+        s.layout = _LAYOUT[sp["layout"]]
+        s.mobile = int(sp["mobile"])
+        s.coincident_with = sp["coincident_with"]
+        s.z_init, s.z_max = sp["z_init"], sp["z_max"]
+        s.cap_ppc = sp.get("cap_ppc") or 0
+        s.ionize_into = sp.get("ionize_into", -1)
+        for z, (ev, q) in enumerate(zip(sp["ionization_ev"], sp["lotz_q"])):
+            s.ionization_ev[z] = ev
+            s.lotz_q[z] = q
+    return arr
+
+
+class TorchAllocator:
+    """Device memory for the library from torch.empty(uint8) blocks, kept
+    alive until the library frees them."""
+
+    def __init__(self, device):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self._alloc = A.ALLOC_FN(self._do_alloc)
+        self._free = A.FREE_FN(self._do_free)
+        self.struct = A.AllocT(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, user):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _do_free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+class Pic:
+    """One simulation on one GPU.  cfg is a workload dictionary (see
+    workloads.py).  stream: a torch.cuda.Stream (default: the current one)."""
+
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, torch_alloc: bool = True):
+        import torch
+        self.lib = A.load()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nsp = len(cfg["species"])
+        self.shape = cfg["grid"]["nx"], cfg["grid"]["ny"], cfg["grid"]["nz"]
+        self._alloc = TorchAllocator(self.device) if torch_alloc else None
+        self._g = grid_struct(cfg)
+        self._s = species_structs(cfg)
+        h = C.c_void_p()
+        rc = self.lib.pic_init(C.byref(h), C.byref(self._g), self._s, self.nsp, _SHAPE[cfg["grid"]["shape"]],
+                               C.byref(self._alloc.struct) if self._alloc else None,
+                               C.c_void_p(self.stream.cuda_stream))
+        A.check(rc, None)
+        self.h = h
+
+    # ------------------------------------------------------------------ life
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ steps
+    def step(self, n: int = 1):
+        A.check(self.lib.pic_step(self.h, int(n)), self.h)
+
+    def moments(self) -> dict:
+        m = A.MomentsT()
+        rc = self.lib.pic_moments(self.h, C.byref(m))
+        d = dict(w_e=m.w_e, w_b=m.w_b, kinetic=list(m.kinetic)[: self.nsp], kinetic_total=m.kinetic_total,
+                 charge_total=m.charge_total, rho_max=m.rho_max, gauss_max=m.gauss_max, divb_max=m.divb_max,
+                 count=list(m.count)[: self.nsp], step=m.step, nonfinite=m.nonfinite)
+        A.check(rc, self.h)
+        return d
+
+    def mark_reference(self):
+        A.check(self.lib.pic_mark_reference(self.h), self.h)
+
+    def timing(self, enable: int = -1) -> dict:
+        t = A.TimingT()
+        A.check(self.lib.pic_timing(self.h, int(enable), C.byref(t)), self.h)
+        return dict(push_ms=t.push_ms, migrate_ms=t.migrate_ms, field_ms=t.field_ms,
+                    push_launches=t.push_launches, push_particles=t.push_particles)
+
+    # ------------------------------------------------------------------ state
+    def count(self, s: int) -> int:
+        n = C.c_int64()
+        A.check(self.lib.pic_particle_count(self.h, s, C.byref(n)), self.h)
+        return n.value
+
+    def get_particles(self, s: int) -> dict:
+        n = self.count(s)
+        out = {k: np.zeros(n, dtype=np.float64) for k in ("x", "y", "z")}
+        out.update({k: np.zeros(n, dtype=np.float32) for k in ("ux", "uy", "uz", "w")})
+        out["id"] = np.zeros(n, dtype=np.int64)
+        out["zstate"] = np.zeros(n, dtype=np.int32)
+        v = self._view(out, n)
+        v.capacity = n
+        A.check(self.lib.pic_get_particles(self.h, s, C.byref(v)), self.h)
+        return out
+
+    def set_particles(self, s: int, p: dict):
+        n = len(p["x"])
+        arr = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("x", "y", "z")}
+        arr.update({k: np.ascontiguousarray(p[k], dtype=np.float32) for k in ("ux", "uy", "uz", "w")})
+        arr["id"] = np.ascontiguousarray(p["id"], dtype=np.int64)
+        arr["zstate"] = np.ascontiguousarray(p["zstate"], dtype=np.int32) if p.get("zstate") is not None else None
+        v = self._view(arr, n)
+        A.check(self.lib.pic_set_particles(self.h, s, C.byref(v)), self.h)
+
+    @staticmethod
+    def _view(a: dict, n: int) -> A.ParticlesViewT:
+        v = A.ParticlesViewT()
+        v.count = n
+        v.capacity = n
+        for k in ("x", "y", "z"):
+            setattr(v, k, a[k].ctypes.data_as(C.POINTER(C.c_double)))
+        for k in ("ux", "uy", "uz", "w"):
+            setattr(v, k, a[k].ctypes.data_as(C.POINTER(C.c_float)))
+        v.id = a["id"].ctypes.data_as(C.POINTER(C.c_int64))
+        if a.get("zstate") is not None:
+            v.zstate = a["zstate"].ctypes.data_as(C.POINTER(C.c_int32))
+        return v
+
+    def get_fields(self):
+        nx, ny, nz = self.shape
+        E, B, J = (np.zeros((3, nz, ny, nx), dtype=np.float32) for _ in range(3))
+        A.check(self.lib.pic_get_fields(self.h, E.ctypes.data, B.ctypes.data, J.ctypes.data), self.h)
+        return E, B, J
+
+    def set_fields(self, E=None, B=None, J=None):
+        nx, ny, nz = self.shape
+        conv = [None if f is None else np.ascontiguousarray(np.asarray(f, dtype=np.float32).reshape(3, nz, ny, nx))
+                for f in (E, B, J)]
+        ptrs = [None if f is None else f.ctypes.data for f in conv]
+        A.check(self.lib.pic_set_fields(self.h, *ptrs), self.h)

@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: every symbol the headers declare is exported, and
+argument errors come back as PIC_ERR_ARG (with a message) before any launch."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1606_02862_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_1606_02862_amd import build
+        build.build()
+    _capi.load()
+    return _capi
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(pic_\w+)\s*\(", text, flags=re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported(A):
+    lib = A.load()
+    names = _declared()
+    assert {"pic_init", "pic_step", "pic_moments", "pic_destroy"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+        assert n in A.SIGNATURES, f"{n} missing from the binding"
+
+
+def _init(A, cfg, shape=None, nsp=None, mutate=None):
+    from paper_1606_02862_amd.pic import grid_struct, species_structs
+    g = grid_struct(cfg)
+    s = species_structs(cfg)
+    if mutate:
+        mutate(g, s)
+    h = C.c_void_p(123)
+    shp = shape if shape is not None else {"cic": 1, "tsc": 2}[cfg["grid"]["shape"]]
+    rc = A.load().pic_init(C.byref(h), C.byref(g), s, len(cfg["species"]) if nsp is None else nsp, shp, None, None)
+    return rc, h, A.load().pic_last_error(None).decode()
+
+
+@pytest.mark.parametrize("what,mutate,needle", [
+    ("nx not a multiple of 8", lambda g, s: setattr(g, "nx", 12), "multiple"),
+    ("nz not a multiple of 4", lambda g, s: setattr(g, "nz", 6), "multiple"),
+    ("Courant", lambda g, s: setattr(g, "dt", 0.6), "Courant"),
+    ("negative dx", lambda g, s: setattr(g, "dx", -1.0), "positive"),
+    ("zero mass", lambda g, s: setattr(s[0], "mass", 0.0), "mass"),
+    ("drift >= c", lambda g, s: s[0].drift_beta.__setitem__(0, 1.0), "drift_beta"),
+    ("bad layout", lambda g, s: setattr(s[0], "layout", 7), "layout"),
+    ("coincident with itself", lambda g, s: setattr(s[0], "coincident_with", 0), "coincident"),
+    ("z_init > z_max", lambda g, s: (setattr(s[0], "z_max", 2), setattr(s[0], "z_init", 3),
+                                     s[0].ionization_ev.__setitem__(0, 1.0), s[0].ionization_ev.__setitem__(1, 2.0)),
+     "z_init"),
+    ("ionize_into without charge states", lambda g, s: setattr(s[0], "ionize_into", 0), "ionize_into"),
+    ("cap below ppc", lambda g, s: setattr(s[0], "cap_ppc", 3), "cap_ppc"),
+])
+def test_init_rejects_bad_arguments(A, what, mutate, needle):
+    rc, h, msg = _init(A, workloads.config(0), mutate=mutate)
+    assert rc == A.PIC_ERR_ARG, what
+    assert h.value is None
+    assert needle in msg, msg
+
+
+def test_init_rejects_bad_shape_and_species_count(A):
+    rc, _, msg = _init(A, workloads.config(0), shape=3)
+    assert rc == A.PIC_ERR_ARG and "shape" in msg
+    rc, _, msg = _init(A, workloads.config(0), nsp=0)
+    assert rc == A.PIC_ERR_ARG and "n_species" in msg
+
+
+def test_null_handles(A):
+    lib = A.load()
+    assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
+    assert lib.pic_destroy(None) == A.PIC_OK
+    assert lib.pic_abi_version() == 1
+    m = A.MomentsT()
+    assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1606_02862_amd import _capi
+    monkeypatch.setattr(_capi, "_lib", None)
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _capi.load()

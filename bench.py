@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Particle-in-cell throughput on one MI355X.
+
+One "step" is one full PIC cycle of the library (pic_step): zero J; per
+supercell gather + relativistic Boris + move + Esirkepov deposit (fused
+kernel); supercell migration; Yee B/2, E, B/2.  The default workload is the
+128^3 CIC electron shear layer (16 particles per cell, 33.6M electrons,
++-0.2c counter-streaming along x, u_th = 0.01c, immobile ions, dt = 0.5,
+particles re-sorted into supercell frames every step).  Inputs are synthetic
+and seeded, generated on the GPU by pic_init, and resident in HBM before the
+timed region starts.
+
+Prints one JSON line: particle updates/s (value), ms per step, the roofline
+of the dominant kernel (the fused particle kernel, HIP-event timed on the
+handle's stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "push_shear128_counters.json")
+PUSH_SOURCE = os.path.join(ROOT, "paper_1606_02862_amd", "csrc", "k_push.hip")
+
+
+def algorithmic_bytes_per_push(n_particles: int, n_cells: int, order: int) -> int:
+    """Bytes one particle-kernel launch must move: per particle 28 B read
+    (x, y, z, ux, uy, uz, w) and 24 B written (x, y, z, ux, uy, uz); per cell
+    E and B read once (24 B) and J read-modify-written once (24 B)."""
+    return n_particles * (28 + 24) + n_cells * (24 + 24)
+
+
+def algorithmic_bytes_per_step(n_particles: int, n_cells: int) -> int:
+    """Whole cycle: the particle kernel's bytes, J zeroed (12 B/cell), and the
+    three Yee passes (each reads 6 and writes 3 components: 36 B/cell, plus J
+    read in the E pass: 12 B/cell)."""
+    return algorithmic_bytes_per_push(n_particles, n_cells, 1) + n_cells * (12 + 3 * 36 + 12)
+
+
+def source_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(n_particles: int):
+    """HBM bytes per push launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, scaled by the copy-kernel calibration; None if absent
+    or if the particle kernel's source changed since they were taken."""
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("k_push_sha256_16") != source_hash(PUSH_SOURCE) or d.get("particles") != n_particles:
+        return None
+    fetch = d["fetch_kib_per_dispatch"] * 1024 / d["fetch_scale"]
+    write = d["write_kib_per_dispatch"] * 1024 / d["write_scale"]
+    return fetch + write
+
+
+def host_description():
+    cpu = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                cpu = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return cpu, os.cpu_count()
+
+
+def cpu_baseline(cfg_idx: int, box: int, steps: int) -> dict:
+    """The FP64 oracle (plain C, one thread) on a sub-box of the same workload."""
+    import oracle
+    cfg = workloads.config(cfg_idx, nx=box, ny=box, nz=box)
+    st = oracle.init_state(cfg)
+    n = sum(s.n for s in st.species if s.mobile)
+    t0 = time.perf_counter()
+    oracle.step(st, steps)
+    dt = time.perf_counter() - t0
+    cpu, ncpu = host_description()
+    return {"value": n * steps / dt, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{box}^3 periodic sub-box of the same workload ({n} particles), {steps} PIC cycles, "
+                      f"FP64 C oracle, single thread; host {cpu}, {ncpu} logical CPUs",
+            "seconds": dt}
+
+
+def copy_calibration() -> int:
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters divided
+    by 1 GiB give the scale that turns the counters into HBM bytes."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "repeats": 3}), flush=True)
+    return 0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=1, help="workload preset (1: 128^3 CIC shear, 2: TSC e+p)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-box", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    args = ap.parse_args(argv)
+    if args.copy_calibration:
+        return copy_calibration()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not implemented "
+                                   "(see DESIGN.md for how the path would shard)", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+
+    import paper_1606_02862_amd as P
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    P.load()
+    cfg = workloads.config(args.config)
+    gc = cfg["grid"]
+    ncell = gc["nx"] * gc["ny"] * gc["nz"]
+    order = {"cic": 1, "tsc": 2}[gc["shape"]]
+    n_particles = sum(ncell * s["ppc"] for s in cfg["species"] if s["mobile"])
+
+    pic = P.Pic(cfg)
+    stream = pic.stream
+    pic.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` cycles, HIP events on the handle's stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    pic.step(args.steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    ms_per_step = ms / args.steps
+
+    # second timed region with per-kernel HIP events for the roofline
+    pic.timing(1)
+    pic.step(args.steps)
+    tm = pic.timing(0)
+    torch.cuda.synchronize()
+    moments = pic.moments()
+    pic.close()
+
+    push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
+    per_launch = algorithmic_bytes_per_push(n_particles // max(1, sum(1 for s in cfg["species"] if s["mobile"])),
+                                            ncell, order)
+    achieved = per_launch / (push_avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(n_particles)
+    step_bytes = algorithmic_bytes_per_step(n_particles, ncell)
+    value = n_particles * args.steps / (ms * 1e-3)
+    line = {
+        "metric": "particle updates/s (gather+push+deposit) & % HBM peak",
+        "value": value,
+        "unit": "particle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox initial state generated on the GPU)",
+        "config": {"workload": cfg["workload"], "grid": [gc["nx"], gc["ny"], gc["nz"]], "shape": gc["shape"],
+                   "species": [{"name": s["name"], "ppc": s["ppc"], "mass": s["mass"]} for s in cfg["species"]],
+                   "particles": n_particles, "supercell": [8, 8, 4], "dt": gc["dt"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_push (gather+Boris+Esirkepov)", "avg_launch_ms": push_avg_ms,
+                     "algorithmic_bytes_per_launch": per_launch},
+        "step_breakdown_ms": {"push": tm["push_ms"] / args.steps, "migrate": tm["migrate_ms"] / args.steps,
+                              "fields": tm["field_ms"] / args.steps},
+        "hbm_frac_whole_step": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "checks": {"gauss_max_over_rho_max": moments["gauss_max"] / max(moments["rho_max"], 1e-30),
+                   "particles_after": sum(moments["count"])},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -7,10 +7,18 @@
 // staged once into LDS; lane l handles slot l of every 256-slot frame, so each
 // frame is read and written with fully coalesced fp32 loads and stores.  The
 // current of all the supercell's particles accumulates in an LDS tile (plus
-// guards) through LDS float atomics and is flushed to global J once, with
-// global float atomics because neighbouring tiles overlap.  Particles that
-// leave the supercell are appended to the destination supercell's arrival
-// list and their slot is recorded as a hole for the migration kernel.
+// guards) and is flushed to global J once, with global float atomics because
+// neighbouring tiles overlap.  Particles that leave the supercell are appended
+// to the destination supercell's arrival list and their slot is recorded as a
+// hole for the migration kernel.
+//
+// The LDS current tile is 64-bit fixed point.  On gfx950 an LDS float atomic
+// add is serialised lane by lane (about 3 CU cycles per active lane, ~190
+// cycles per wave64 instruction) while 64-bit integer LDS atomics issue in
+// ~8-14 cycles per wave instruction.  Each contribution is scaled by
+// 2^30 / vmax (vmax bounds any single contribution: |q w| dx_d / (dV dt)),
+// rounded to int32 and added as int64, so the tile sums are exact and
+// independent of the order of the atomics; the flush converts once to fp32.
 #include "pic_device.hpp"
 
 namespace pic {
@@ -75,13 +83,20 @@ __device__ inline int esirkepov_axis(float x0, float x1, float* S0, float* DS)
     return m;
 }
 
-template <int ORDER, bool HAS_Z>
-__global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
+// Fixed-point contribution: round(v * scale) as a sign-extended 64-bit integer.
+__device__ inline void jadd(unsigned long long* p, float v, float scale)
+{
+    const int iv = __float2int_rn(v * scale);
+    atomicAdd(p, (unsigned long long)(long long)iv);
+}
+
+template <int ORDER, bool HAS_Z, int NT>
+__global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float jscale, float jinv)
 {
     using T = Tile<ORDER>;
     __shared__ float fE[3][T::GN];
     __shared__ float fB[3][T::GN];
-    __shared__ float tJ[3][T::JN];
+    __shared__ unsigned long long tJ[3][T::JN];
     __shared__ int s_holes;
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
@@ -91,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
     const int N = g.nx * g.ny * g.nz;
 
     // ---- stage E, B with guards; zero the current tile
-    for (int t = tid; t < T::GN; t += BLOCK) {
+    for (int t = tid; t < T::GN; t += NT) {
         const int tx = t % T::GX, ty = (t / T::GX) % T::GY, tz = t / (T::GX * T::GY);
         int gx = ox + tx - 1, gy = oy + ty - 1, gz = oz + tz - 1;
         gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
@@ -104,7 +119,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
             fB[c][t] = g.B[c * N + gi];
         }
     }
-    for (int t = tid; t < 3 * T::JN; t += BLOCK) (&tJ[0][0])[t] = 0.0f;
+    for (int t = tid; t < 3 * T::JN; t += NT) (&tJ[0][0])[t] = 0ull;
     if (tid == 0) s_holes = 0;
     __syncthreads();
 
@@ -117,7 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
     const float third = 1.0f / 3.0f;
     bool bad = false;
 
-    for (int f = 0; f < n; f += BLOCK) {
+    for (int f = 0; f < n; f += NT) {
         const int slot = f + tid;
         if (slot >= n) break;
         const int64_t p = base + slot;
@@ -169,51 +184,54 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
             const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
             const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
             const float qw = q * wgt;
-            // J_x: running sum along x of DSx * (S0y S0z + DSy S0z / 2 + S0y DSz / 2 + DSy DSz / 3)
+            // Esirkepov weights, factored: for the x current
+            //   A(b,c) = S0y S0z + (DSy S0z + S0y DSz)/2 + DSy DSz/3
+            //          = (S0y + DSy/2) S0z + (S0y/2 + DSy/3) DSz,
+            // and cyclically for y and z.
+            float Px[T::W], Qx[T::W], Py[T::W], Qy[T::W], Pz[T::W], Qz[T::W];
+#pragma unroll
+            for (int k = 0; k < T::W; ++k) {
+                Px[k] = fmaf(0.5f, DSx[k], S0x[k]); Qx[k] = fmaf(third, DSx[k], 0.5f * S0x[k]);
+                Py[k] = fmaf(0.5f, DSy[k], S0y[k]); Qy[k] = fmaf(third, DSy[k], 0.5f * S0y[k]);
+                Pz[k] = fmaf(0.5f, DSz[k], S0z[k]); Qz[k] = fmaf(third, DSz[k], 0.5f * S0z[k]);
+            }
+            // running sums of DS along each axis (the last one is zero)
+            float Rx[T::W - 1], Ry[T::W - 1], Rz[T::W - 1];
+            Rx[0] = DSx[0]; Ry[0] = DSy[0]; Rz[0] = DSz[0];
+#pragma unroll
+            for (int k = 1; k < T::W - 1; ++k) {
+                Rx[k] = Rx[k - 1] + DSx[k]; Ry[k] = Ry[k - 1] + DSy[k]; Rz[k] = Rz[k - 1] + DSz[k];
+            }
+            const float cx = jcx * qw, cy = jcy * qw, cz = jcz * qw;
+            unsigned long long* Jx = &tJ[0][0];
+            unsigned long long* Jy = &tJ[1][0];
+            unsigned long long* Jz = &tJ[2][0];
 #pragma unroll
             for (int c = 0; c < T::W; ++c)
 #pragma unroll
                 for (int b = 0; b < T::W; ++b) {
-                    const float A = S0y[b] * S0z[c] + 0.5f * (DSy[b] * S0z[c] + S0y[b] * DSz[c]) +
-                                    third * DSy[b] * DSz[c];
-                    const float cA = jcx * qw * A;
-                    float acc = 0.0f;
+                    const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
+                    const float ax = cx * fmaf(Py[b], S0z[c], Qy[b] * DSz[c]);
 #pragma unroll
-                    for (int a = 0; a < T::W - 1; ++a) {
-                        acc += DSx[a];
-                        const float v = cA * acc;
-                        if (v != 0.0f) atomicAdd(&tJ[0][((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], v);
-                    }
+                    for (int a = 0; a < T::W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a], jscale);
                 }
 #pragma unroll
             for (int c = 0; c < T::W; ++c)
 #pragma unroll
                 for (int a = 0; a < T::W; ++a) {
-                    const float A = S0z[c] * S0x[a] + 0.5f * (DSz[c] * S0x[a] + S0z[c] * DSx[a]) +
-                                    third * DSz[c] * DSx[a];
-                    const float cA = jcy * qw * A;
-                    float acc = 0.0f;
+                    const float ay = cy * fmaf(Pz[c], S0x[a], Qz[c] * DSx[a]);
 #pragma unroll
-                    for (int b = 0; b < T::W - 1; ++b) {
-                        acc += DSy[b];
-                        const float v = cA * acc;
-                        if (v != 0.0f) atomicAdd(&tJ[1][((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], v);
-                    }
+                    for (int b = 0; b < T::W - 1; ++b)
+                        jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b], jscale);
                 }
 #pragma unroll
             for (int b = 0; b < T::W; ++b)
 #pragma unroll
                 for (int a = 0; a < T::W; ++a) {
-                    const float A = S0x[a] * S0y[b] + 0.5f * (DSx[a] * S0y[b] + S0x[a] * DSy[b]) +
-                                    third * DSx[a] * DSy[b];
-                    const float cA = jcz * qw * A;
-                    float acc = 0.0f;
+                    const float az = cz * fmaf(Px[a], S0y[b], Qx[a] * DSy[b]);
 #pragma unroll
-                    for (int c = 0; c < T::W - 1; ++c) {
-                        acc += DSz[c];
-                        const float v = cA * acc;
-                        if (v != 0.0f) atomicAdd(&tJ[2][((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], v);
-                    }
+                    for (int c = 0; c < T::W - 1; ++c)
+                        jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c], jscale);
                 }
         }
 
@@ -253,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
     __syncthreads();
 
     // ---- flush the current tile (guards overlap neighbouring supercells)
-    for (int t = tid; t < T::JN; t += BLOCK) {
+    for (int t = tid; t < T::JN; t += NT) {
         const int tx = t % T::JX, ty = (t / T::JX) % T::JY, tz = t / (T::JX * T::JY);
         int gx = ox + tx - T::JL, gy = oy + ty - T::JL, gz = oz + tz - T::JL;
         gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
@@ -262,8 +280,8 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
         const int gi = gx + g.nx * (gy + g.ny * gz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float v = tJ[c][t];
-            if (v != 0.0f) unsafeAtomicAdd(&g.J[c * N + gi], v);
+            const long long iv = (long long)tJ[c][t];
+            if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
         }
     }
     if (tid == 0) {
@@ -273,16 +291,19 @@ __global__ __launch_bounds__(BLOCK) void k_push(GridView g, SpeciesView s)
     }
 }
 
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, hipStream_t st)
+hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, hipStream_t st)
 {
-    const dim3 grid(g.nsc), block(BLOCK);
+    const dim3 grid(g.nsc);
     const bool hz = s.zs != nullptr;
+    // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
+    const float jscale = vmax > 0.0f ? 1073741824.0f / vmax : 1.0f;
+    const float jinv = 1.0f / jscale;
     if (order == 1) {
-        if (hz) hipLaunchKernelGGL((k_push<1, true>), grid, block, 0, st, g, s);
-        else hipLaunchKernelGGL((k_push<1, false>), grid, block, 0, st, g, s);
+        if (hz) hipLaunchKernelGGL((k_push<1, true, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv);
+        else hipLaunchKernelGGL((k_push<1, false, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv);
     } else {
-        if (hz) hipLaunchKernelGGL((k_push<2, true>), grid, block, 0, st, g, s);
-        else hipLaunchKernelGGL((k_push<2, false>), grid, block, 0, st, g, s);
+        if (hz) hipLaunchKernelGGL((k_push<2, true, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv);
+        else hipLaunchKernelGGL((k_push<2, false, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv);
     }
     return hipGetLastError();
 }

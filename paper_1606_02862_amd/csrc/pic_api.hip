@@ -247,6 +247,16 @@ int collect_timing(pic_ctx* c)
     return PIC_OK;
 }
 
+// Bound of one particle's current contribution, |q w| max(dx, dy, dz) / (dV dt).
+double push_vmax(const pic_ctx* c, int s)
+{
+    const Species& S = c->sp[s];
+    const pic_grid_t& g = c->grid;
+    const double qmax = std::fabs(S.desc.charge) * (S.desc.z_max > 0 ? S.desc.z_max : 1);
+    const double dmax = std::max(g.dx, std::max(g.dy, g.dz));
+    return qmax * S.wmax * dmax / (g.dx * g.dy * g.dz * g.dt);
+}
+
 int64_t host_count(pic_ctx* c, int s, std::vector<int32_t>& counts)
 {
     counts.resize(c->g.nsc);
@@ -332,6 +342,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         S.id_offset = off;
         S.n_init = N * species[s].ppc;
         S.weight = species[s].ppc > 0 ? species[s].density * dV / species[s].ppc : 0.0;
+        S.wmax = S.weight;
         off += S.n_init;
     }
     for (int s = 0; s < n_species; ++s) {
@@ -389,7 +400,7 @@ int pic_step(pic_ctx* c, int n)
         HIPCHK(c, launch_zero_f32(c->g.J, 3 * N, c->stream));
         for (int s = 0; s < c->nsp; ++s) {
             if (!c->sp[s].desc.mobile) continue;
-            HIPCHK(c, launch_push(c->g, c->sp[s].v, c->order, c->stream));
+            HIPCHK(c, launch_push(c->g, c->sp[s].v, c->order, (float)push_vmax(c, s), c->stream));
             c->pending_launches += c->timing ? 1 : 0;
         }
         if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -549,6 +560,7 @@ int pic_set_particles(pic_ctx* c, int s, const pic_particles_view_t* v)
     std::vector<uint32_t> ids(n, 0);
     std::vector<uint8_t> zs(sv.zs ? n : 0, 0);
     const float lim[3] = {XMAX, YMAX, ZMAX};
+    double wmax = 0.0;
     for (int64_t k = 0; k < v->count; ++k) {
         const double p[3] = {v->x[k], v->y[k], v->z[k]};
         const int dims[3] = {g.nx, g.ny, g.nz}, sdim[3] = {SX, SY, SZ};
@@ -567,6 +579,7 @@ int pic_set_particles(pic_ctx* c, int s, const pic_particles_view_t* v)
         if (v->id[k] < 0 || v->id[k] > 0xFFFFFFFFLL) return fail(c, PIC_ERR_ARG, "particle %lld: id out of range", (long long)k);
         const int sc = sci[0] + g.ncx * (sci[1] + g.ncy * sci[2]);
         if (cnt[sc] >= sv.cap) return fail(c, PIC_ERR_CAPACITY, "supercell %d holds more than %d particles", sc, sv.cap);
+        wmax = std::max(wmax, (double)std::fabs(v->w[k]));
         const size_t q = (size_t)sc * sv.cap + cnt[sc]++;
         a[0][q] = rel[0]; a[1][q] = rel[1]; a[2][q] = rel[2];
         a[3][q] = v->ux[k]; a[4][q] = v->uy[k]; a[5][q] = v->uz[k]; a[6][q] = v->w[k];
@@ -583,6 +596,7 @@ int pic_set_particles(pic_ctx* c, int s, const pic_particles_view_t* v)
     if (sv.zs) HIPCHK(c, hipMemcpyAsync(sv.zs, zs.data(), n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(sv.count, cnt.data(), (size_t)g.nsc * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->sp[s].wmax = wmax;
     return PIC_OK;
 }
 

@@ -62,6 +62,7 @@ struct Species {
     int64_t n_init;        // particles at t = 0
     int64_t id_offset;     // first id at t = 0
     double weight;
+    double wmax;           // largest |w| the species may hold (fixed-point current scale)
 };
 
 // Map a workgroup index to a supercell so that the 8 XCDs (which receive
@@ -82,7 +83,8 @@ hipError_t launch_init_species(const GridView& g, const SpeciesView& s, uint64_t
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, hipStream_t st);
+// vmax: upper bound of |q w| max(dx,dy,dz) / (dV dt) over the species' particles
+hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, hipStream_t st);
 hipError_t launch_migrate(const GridView& g, const SpeciesView& s, hipStream_t st);
 hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st);
 hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st);

@@ -2,23 +2,31 @@
 // relativistic Boris push, move, and Esirkepov charge-conserving current
 // deposition, fused in one pass over the supercell's frames.
 //
-// One 256-lane workgroup (4 wave64) per supercell, the paper's
-// block-per-supercell mapping.  E and B for the supercell plus guard nodes are
-// staged once into LDS; lane l handles slot l of every 256-slot frame, so each
-// frame is read and written with fully coalesced fp32 loads and stores.  The
-// current of all the supercell's particles accumulates in an LDS tile (plus
-// guards) and is flushed to global J once, with global float atomics because
-// neighbouring tiles overlap.  Particles that leave the supercell are appended
-// to the destination supercell's arrival list and their slot is recorded as a
-// hole for the migration kernel.
+// One workgroup per supercell, the paper's block-per-supercell mapping.  E
+// and B for the supercell plus guard nodes are staged once into LDS; lane l
+// handles slot l of every frame, so frames are read and written with fully
+// coalesced fp32 loads and stores.  The current of all the supercell's
+// particles accumulates in an LDS tile (plus guards) and is flushed to global
+// J once, with global float atomics because neighbouring tiles overlap.
+// Particles that leave the supercell are appended to the destination
+// supercell's arrival list and their slot is recorded as a hole for the
+// migration kernel.
 //
-// The LDS current tile is 64-bit fixed point.  On gfx950 an LDS float atomic
-// add is serialised lane by lane (about 3 CU cycles per active lane, ~190
-// cycles per wave64 instruction) while 64-bit integer LDS atomics issue in
-// ~8-14 cycles per wave instruction.  Each contribution is scaled by
-// 2^30 / vmax (vmax bounds any single contribution: |q w| dx_d / (dV dt)),
-// rounded to int32 and added as int64, so the tile sums are exact and
-// independent of the order of the atomics; the flush converts once to fp32.
+// Current tile in 64-bit fixed point: on gfx950 an LDS float atomic add is
+// serialised lane by lane (about 3 CU cycles per active lane, ~190 cycles per
+// wave64 instruction) while 64-bit integer LDS atomics issue in ~8-14 cycles
+// per wave instruction whatever the number of active lanes.  Each
+// contribution is scaled by 2^30 / vmax (vmax bounds any single contribution:
+// |q w| dx_d / (dV dt)), rounded to int32 and added as int64, so tile sums are
+// exact and independent of the order of the atomics; the flush converts once.
+//
+// Two deposit paths (same Esirkepov arithmetic): a particle whose first shape
+// node is unchanged on all three axes (it stays in its cell for CIC, keeps its
+// nearest node for TSC) needs only an (ORDER+1)-node window per axis, which
+// is done in line (CIC: 12 atomics instead of 54).  The others are queued in
+// a per-supercell scratch list (wave ballot + popcount for the slots) and
+// deposited after the frame loop with the full (ORDER+2)-node window, so that
+// no wave runs the wide window for a few of its lanes.
 #include "pic_device.hpp"
 
 namespace pic {
@@ -33,7 +41,7 @@ struct Tile {
     static constexpr int JX = SX + 2 * ORDER + 1, JY = SY + 2 * ORDER + 1, JZ = SZ + 2 * ORDER + 1;
     static constexpr int JN = JX * JY * JZ;
     static constexpr int NP = ORDER + 1;  // shape points per axis
-    static constexpr int W = ORDER + 2;   // Esirkepov window per axis
+    static constexpr int W = ORDER + 2;   // Esirkepov window per axis (general case)
 };
 
 // Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f.
@@ -59,7 +67,7 @@ __device__ inline float interp(const float* f, int ix, int iy, int iz, const flo
     return acc;
 }
 
-// Old and new shape on the Esirkepov window [m, m + W) of one axis.
+// Old shape and shape change on the general window [m, m + W) of one axis.
 template <int ORDER>
 __device__ inline int esirkepov_axis(float x0, float x1, float* S0, float* DS)
 {
@@ -83,24 +91,81 @@ __device__ inline int esirkepov_axis(float x0, float x1, float* S0, float* DS)
     return m;
 }
 
-// Fixed-point contribution: round(v * scale) as a sign-extended 64-bit integer.
+// Fixed-point contribution: round(v * scale) added as a sign-extended int64.
 __device__ inline void jadd(unsigned long long* p, float v, float scale)
 {
     const int iv = __float2int_rn(v * scale);
     atomicAdd(p, (unsigned long long)(long long)iv);
 }
 
+// Esirkepov deposit of one particle on a window of W nodes per axis starting
+// at tile nodes (mx, my, mz):
+//   W_x(a,b,c) = DSx_a [S0y_b S0z_c + (DSy_b S0z_c + S0y_b DSz_c)/2 + DSy_b DSz_c/3]
+//   J_x(a+1/2, b, c) = -(q w dx / (dV dt)) sum_{a' <= a} W_x(a',b,c)
+// (cyclically for y and z), with the transverse factor written as
+// (S0y + DSy/2) S0z + (S0y/2 + DSy/3) DSz.
+template <int ORDER, int W>
+__device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, const float* S0x, const float* DSx,
+                               const float* S0y, const float* DSy, const float* S0z, const float* DSz, float cx,
+                               float cy, float cz, float jscale)
+{
+    using T = Tile<ORDER>;
+    const float third = 1.0f / 3.0f;
+    float Px[W], Qx[W], Py[W], Qy[W], Pz[W], Qz[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        Px[k] = fmaf(0.5f, DSx[k], S0x[k]); Qx[k] = fmaf(third, DSx[k], 0.5f * S0x[k]);
+        Py[k] = fmaf(0.5f, DSy[k], S0y[k]); Qy[k] = fmaf(third, DSy[k], 0.5f * S0y[k]);
+        Pz[k] = fmaf(0.5f, DSz[k], S0z[k]); Qz[k] = fmaf(third, DSz[k], 0.5f * S0z[k]);
+    }
+    float Rx[W - 1], Ry[W - 1], Rz[W - 1];  // running sums of DS (the last one is zero)
+    Rx[0] = DSx[0]; Ry[0] = DSy[0]; Rz[0] = DSz[0];
+#pragma unroll
+    for (int k = 1; k < W - 1; ++k) {
+        Rx[k] = Rx[k - 1] + DSx[k]; Ry[k] = Ry[k - 1] + DSy[k]; Rz[k] = Rz[k - 1] + DSz[k];
+    }
+    unsigned long long* Jx = tJ;
+    unsigned long long* Jy = tJ + T::JN;
+    unsigned long long* Jz = tJ + 2 * T::JN;
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
+            const float ax = cx * fmaf(Py[b], S0z[c], Qy[b] * DSz[c]);
+#pragma unroll
+            for (int a = 0; a < W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a], jscale);
+        }
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const float ay = cy * fmaf(Pz[c], S0x[a], Qz[c] * DSx[a]);
+#pragma unroll
+            for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b], jscale);
+        }
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const float az = cz * fmaf(Px[a], S0y[b], Qx[a] * DSy[b]);
+#pragma unroll
+            for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c], jscale);
+        }
+}
+
 template <int ORDER, bool HAS_Z, int NT>
-__global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float jscale, float jinv)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_push(GridView g, SpeciesView s, float jscale, float jinv)
 {
     using T = Tile<ORDER>;
     __shared__ float fE[3][T::GN];
     __shared__ float fB[3][T::GN];
-    __shared__ unsigned long long tJ[3][T::JN];
-    __shared__ int s_holes;
+    __shared__ unsigned long long tJ[3 * T::JN];
+    __shared__ int s_holes, s_queue;
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     const int ox = scx * SX, oy = scy * SY, oz = scz * SZ;
     const int N = g.nx * g.ny * g.nz;
@@ -119,28 +184,45 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
             fB[c][t] = g.B[c * N + gi];
         }
     }
-    for (int t = tid; t < 3 * T::JN; t += NT) (&tJ[0][0])[t] = 0ull;
-    if (tid == 0) s_holes = 0;
+    for (int t = tid; t < 3 * T::JN; t += NT) tJ[t] = 0ull;
+    if (tid == 0) { s_holes = 0; s_queue = 0; }
     __syncthreads();
 
     const int n = s.count[sc];
     const int64_t base = (int64_t)sc * s.cap;
+    const int64_t qbase = (int64_t)sc * g.qcap;
+    const int64_t qstride = (int64_t)g.nsc * g.qcap;
     const float dt = g.dt;
     const float cdx = dt / g.dx, cdy = dt / g.dy, cdz = dt / g.dz;
     const float inv_dvdt = 1.0f / (g.dx * g.dy * g.dz * dt);
     const float jcx = -g.dx * inv_dvdt, jcy = -g.dy * inv_dvdt, jcz = -g.dz * inv_dvdt;
-    const float third = 1.0f / 3.0f;
+    const float qm = 0.5f * dt / s.mass;
     bool bad = false;
 
+    // software pipeline: the next frame's particle is loaded while this one is computed
+    float nx0 = 0.f, ny0 = 0.f, nz0 = 0.f, nux = 0.f, nuy = 0.f, nuz = 0.f, nw = 0.f;
+    int nzs = 0;
+    if (tid < n) {
+        const int64_t p = base + tid;
+        nx0 = s.x[p]; ny0 = s.y[p]; nz0 = s.z[p];
+        nux = s.ux[p]; nuy = s.uy[p]; nuz = s.uz[p]; nw = s.w[p];
+        if constexpr (HAS_Z) nzs = s.zs[p];
+    }
     for (int f = 0; f < n; f += NT) {
         const int slot = f + tid;
         if (slot >= n) break;
         const int64_t p = base + slot;
-        const float x0 = s.x[p], y0 = s.y[p], z0 = s.z[p];
-        float ux = s.ux[p], uy = s.uy[p], uz = s.uz[p];
-        const float wgt = s.w[p];
+        const float x0 = nx0, y0 = ny0, z0 = nz0;
+        float ux = nux, uy = nuy, uz = nuz;
+        const float wgt = nw;
         float q = s.charge;
-        if constexpr (HAS_Z) q *= (float)s.zs[p];
+        if constexpr (HAS_Z) q *= (float)nzs;
+        if (slot + NT < n) {
+            const int64_t pn = p + NT;
+            nx0 = s.x[pn]; ny0 = s.y[pn]; nz0 = s.z[pn];
+            nux = s.ux[pn]; nuy = s.uy[pn]; nuz = s.uz[pn]; nw = s.w[pn];
+            if constexpr (HAS_Z) nzs = s.zs[pn];
+        }
 
         // ---- gather at node-centred and half-shifted positions per axis
         float wnx[T::NP], wny[T::NP], wnz[T::NP], wsx[T::NP], wsy[T::NP], wsz[T::NP];
@@ -155,12 +237,11 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
         const float Bz = interp<ORDER>(fB[2], isx, isy, inz, wsx, wsy, wnz) + g.b0z;
 
         // ---- relativistic Boris: half kick, rotation, half kick
-        const float h = 0.5f * q / s.mass * dt;
+        const float h = q * qm;
         const float umx = fmaf(h, Ex, ux), umy = fmaf(h, Ey, uy), umz = fmaf(h, Ez, uz);
-        const float gm = sqrtf(1.0f + umx * umx + umy * umy + umz * umz);
-        const float hg = h / gm;
+        const float hg = h * __builtin_amdgcn_rsqf(1.0f + umx * umx + umy * umy + umz * umz);
         const float tx = hg * Bx, ty = hg * By, tz = hg * Bz;
-        const float sf = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+        const float sf = 2.0f * __builtin_amdgcn_rcpf(1.0f + tx * tx + ty * ty + tz * tz);
         const float upx = umx + (umy * tz - umz * ty);
         const float upy = umy + (umz * tx - umx * tz);
         const float upz = umz + (umx * ty - umy * tx);
@@ -169,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
         uz = fmaf(h, Ez, umz + sf * (upx * ty - upy * tx));
 
         // ---- move
-        const float ig = 1.0f / sqrtf(1.0f + ux * ux + uy * uy + uz * uz);
+        const float ig = __builtin_amdgcn_rsqf(1.0f + ux * ux + uy * uy + uz * uz);
         const float ddx = cdx * ux * ig, ddy = cdy * uy * ig, ddz = cdz * uz * ig;
         if (!(fabsf(ddx) < 1.0f && fabsf(ddy) < 1.0f && fabsf(ddz) < 1.0f)) {
             bad = true;  // a displacement of a cell or more (or NaN): keep the particle where it was
@@ -177,97 +258,112 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
         }
         const float x1 = x0 + ddx, y1 = y0 + ddy, z1 = z0 + ddz;
 
-        // ---- Esirkepov current into the LDS tile
-        {
-            float S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
-            const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + T::JL;
-            const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
-            const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
-            const float qw = q * wgt;
-            // Esirkepov weights, factored: for the x current
-            //   A(b,c) = S0y S0z + (DSy S0z + S0y DSz)/2 + DSy DSz/3
-            //          = (S0y + DSy/2) S0z + (S0y/2 + DSy/3) DSz,
-            // and cyclically for y and z.
-            float Px[T::W], Qx[T::W], Py[T::W], Qy[T::W], Pz[T::W], Qz[T::W];
+        // ---- current: in line when the first shape node is unchanged on every axis
+        const float qw = q * wgt;
+        float w1x[T::NP], w1y[T::NP], w1z[T::NP];
+        const int fx1 = shape_weights<ORDER>(x1, w1x);
+        const int fy1 = shape_weights<ORDER>(y1, w1y);
+        const int fz1 = shape_weights<ORDER>(z1, w1z);
+        const bool same = (fx1 == inx) && (fy1 == iny) && (fz1 == inz);
+        if (same) {
+            float DSx[T::NP], DSy[T::NP], DSz[T::NP];
 #pragma unroll
-            for (int k = 0; k < T::W; ++k) {
-                Px[k] = fmaf(0.5f, DSx[k], S0x[k]); Qx[k] = fmaf(third, DSx[k], 0.5f * S0x[k]);
-                Py[k] = fmaf(0.5f, DSy[k], S0y[k]); Qy[k] = fmaf(third, DSy[k], 0.5f * S0y[k]);
-                Pz[k] = fmaf(0.5f, DSz[k], S0z[k]); Qz[k] = fmaf(third, DSz[k], 0.5f * S0z[k]);
+            for (int k = 0; k < T::NP; ++k) {
+                DSx[k] = w1x[k] - wnx[k];
+                DSy[k] = w1y[k] - wny[k];
+                DSz[k] = w1z[k] - wnz[k];
             }
-            // running sums of DS along each axis (the last one is zero)
-            float Rx[T::W - 1], Ry[T::W - 1], Rz[T::W - 1];
-            Rx[0] = DSx[0]; Ry[0] = DSy[0]; Rz[0] = DSz[0];
-#pragma unroll
-            for (int k = 1; k < T::W - 1; ++k) {
-                Rx[k] = Rx[k - 1] + DSx[k]; Ry[k] = Ry[k - 1] + DSy[k]; Rz[k] = Rz[k - 1] + DSz[k];
+            deposit<ORDER, T::NP>(tJ, inx + T::JL, iny + T::JL, inz + T::JL, wnx, DSx, wny, DSy, wnz, DSz,
+                                  jcx * qw, jcy * qw, jcz * qw, jscale);
+        }
+        // queue the others (contiguous slots per wave from one LDS atomic)
+        const unsigned long long qmask = __ballot(!same);
+        if (qmask) {
+            const int leader = __ffsll((long long)qmask) - 1;
+            int qb = 0;
+            if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
+            qb = __shfl(qb, leader, 64);
+            if (!same) {
+                const int64_t e = qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull));
+                g.qbuf[e] = x0; g.qbuf[e + qstride] = y0; g.qbuf[e + 2 * qstride] = z0;
+                g.qbuf[e + 3 * qstride] = x1; g.qbuf[e + 4 * qstride] = y1; g.qbuf[e + 5 * qstride] = z1;
+                g.qbuf[e + 6 * qstride] = qw;
             }
-            const float cx = jcx * qw, cy = jcy * qw, cz = jcz * qw;
-            unsigned long long* Jx = &tJ[0][0];
-            unsigned long long* Jy = &tJ[1][0];
-            unsigned long long* Jz = &tJ[2][0];
-#pragma unroll
-            for (int c = 0; c < T::W; ++c)
-#pragma unroll
-                for (int b = 0; b < T::W; ++b) {
-                    const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
-                    const float ax = cx * fmaf(Py[b], S0z[c], Qy[b] * DSz[c]);
-#pragma unroll
-                    for (int a = 0; a < T::W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a], jscale);
-                }
-#pragma unroll
-            for (int c = 0; c < T::W; ++c)
-#pragma unroll
-                for (int a = 0; a < T::W; ++a) {
-                    const float ay = cy * fmaf(Pz[c], S0x[a], Qz[c] * DSx[a]);
-#pragma unroll
-                    for (int b = 0; b < T::W - 1; ++b)
-                        jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b], jscale);
-                }
-#pragma unroll
-            for (int b = 0; b < T::W; ++b)
-#pragma unroll
-                for (int a = 0; a < T::W; ++a) {
-                    const float az = cz * fmaf(Px[a], S0y[b], Qx[a] * DSy[b]);
-#pragma unroll
-                    for (int c = 0; c < T::W - 1; ++c)
-                        jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c], jscale);
-                }
         }
 
-        // ---- store, or hand the particle to its new supercell
-        const int mvx = (x1 < 0.0f) ? -1 : (x1 >= (float)SX ? 1 : 0);
-        const int mvy = (y1 < 0.0f) ? -1 : (y1 >= (float)SY ? 1 : 0);
-        const int mvz = (z1 < 0.0f) ? -1 : (z1 >= (float)SZ ? 1 : 0);
-        if ((mvx | mvy | mvz) == 0) {
-            s.x[p] = x1; s.y[p] = y1; s.z[p] = z1;
-            s.ux[p] = ux; s.uy[p] = uy; s.uz[p] = uz;
-        } else {
-            int dx_ = scx + mvx, dy_ = scy + mvy, dz_ = scz + mvz;
-            dx_ += (dx_ < 0) ? g.ncx : 0; dx_ -= (dx_ >= g.ncx) ? g.ncx : 0;
-            dy_ += (dy_ < 0) ? g.ncy : 0; dy_ -= (dy_ >= g.ncy) ? g.ncy : 0;
-            dz_ += (dz_ < 0) ? g.ncz : 0; dz_ -= (dz_ >= g.ncz) ? g.ncz : 0;
-            const int dest = dx_ + g.ncx * (dy_ + g.ncy * dz_);
-            // shift into the destination's frame; x - (-8) can round up onto the far face
-            const float nx1 = fminf(x1 - (float)(mvx * SX), XMAX);
-            const float ny1 = fminf(y1 - (float)(mvy * SY), YMAX);
-            const float nz1 = fminf(z1 - (float)(mvz * SZ), ZMAX);
-            const int k = atomicAdd(&s.in_count[dest], 1);
-            if (k < s.cap_in) {
-                const int64_t q_ = (int64_t)dest * s.cap_in + k;
-                s.ix[q_] = nx1; s.iy[q_] = ny1; s.iz[q_] = nz1;
-                s.iux[q_] = ux; s.iuy[q_] = uy; s.iuz[q_] = uz;
-                s.iw[q_] = wgt;
-                s.iid[q_] = s.id[p];
-                if constexpr (HAS_Z) s.izs[q_] = s.zs[p];
-            } else {
-                g.flags[FLAG_MIGRATE] = 1;
+        // ---- store in place; a particle that left the supercell keeps its
+        // unshifted position here and its slot goes on the hole list, handed
+        // over after the frame loop so no wave waits on a global atomic here
+        s.x[p] = x1; s.y[p] = y1; s.z[p] = z1;
+        s.ux[p] = ux; s.uy[p] = uy; s.uz[p] = uz;
+        const bool left = (x1 < 0.0f) || (x1 >= (float)SX) || (y1 < 0.0f) || (y1 >= (float)SY) || (z1 < 0.0f) ||
+                          (z1 >= (float)SZ);
+        const unsigned long long lmask = __ballot(left);
+        if (lmask) {
+            const int leader = __ffsll((long long)lmask) - 1;
+            int hb = 0;
+            if (lane == leader) hb = atomicAdd(&s_holes, __popcll(lmask));
+            hb = __shfl(hb, leader, 64);
+            const int hidx = hb + __popcll(lmask & ((1ull << lane) - 1ull));
+            if (left) {
+                if (hidx < s.cap_in) {
+                    s.holes[(int64_t)sc * s.cap_in + hidx] = slot;
+                } else {
+                    // hole list full (reported through FLAG_MIGRATE below): keep the
+                    // particle inside its supercell so every later access stays in bounds
+                    s.x[p] = fminf(fmaxf(x1, 0.0f), XMAX);
+                    s.y[p] = fminf(fmaxf(y1, 0.0f), YMAX);
+                    s.z[p] = fminf(fmaxf(z1, 0.0f), ZMAX);
+                }
             }
-            const int hidx = atomicAdd(&s_holes, 1);
-            if (hidx < s.cap_in) s.holes[(int64_t)sc * s.cap_in + hidx] = slot;
         }
     }
     if (bad) g.flags[FLAG_CFL] = 1;
+    __syncthreads();
+
+    // ---- queued particles: general (ORDER+2)-node window, all lanes busy
+    const int nq = s_queue;
+    for (int t = tid; t < nq; t += NT) {
+        const int64_t e = qbase + t;
+        const float x0 = g.qbuf[e], y0 = g.qbuf[e + qstride], z0 = g.qbuf[e + 2 * qstride];
+        const float x1 = g.qbuf[e + 3 * qstride], y1 = g.qbuf[e + 4 * qstride], z1 = g.qbuf[e + 5 * qstride];
+        const float qw = g.qbuf[e + 6 * qstride];
+        float S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
+        const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + T::JL;
+        const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
+        const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
+        deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw, jscale);
+    }
+
+    // ---- hand the leavers to their destination supercells' arrival lists
+    const int nh = min(s_holes, s.cap_in);
+    for (int t = tid; t < nh; t += NT) {
+        const int slot = s.holes[(int64_t)sc * s.cap_in + t];
+        const int64_t p = base + slot;
+        const float x1 = s.x[p], y1 = s.y[p], z1 = s.z[p];
+        const int mvx = (x1 < 0.0f) ? -1 : (x1 >= (float)SX ? 1 : 0);
+        const int mvy = (y1 < 0.0f) ? -1 : (y1 >= (float)SY ? 1 : 0);
+        const int mvz = (z1 < 0.0f) ? -1 : (z1 >= (float)SZ ? 1 : 0);
+        int dx_ = scx + mvx, dy_ = scy + mvy, dz_ = scz + mvz;
+        dx_ += (dx_ < 0) ? g.ncx : 0; dx_ -= (dx_ >= g.ncx) ? g.ncx : 0;
+        dy_ += (dy_ < 0) ? g.ncy : 0; dy_ -= (dy_ >= g.ncy) ? g.ncy : 0;
+        dz_ += (dz_ < 0) ? g.ncz : 0; dz_ -= (dz_ >= g.ncz) ? g.ncz : 0;
+        const int dest = dx_ + g.ncx * (dy_ + g.ncy * dz_);
+        const int k = atomicAdd(&s.in_count[dest], 1);
+        if (k < s.cap_in) {
+            const int64_t q_ = (int64_t)dest * s.cap_in + k;
+            // shift into the destination's frame; x - (-8) can round up onto the far face
+            s.ix[q_] = fminf(x1 - (float)(mvx * SX), XMAX);
+            s.iy[q_] = fminf(y1 - (float)(mvy * SY), YMAX);
+            s.iz[q_] = fminf(z1 - (float)(mvz * SZ), ZMAX);
+            s.iux[q_] = s.ux[p]; s.iuy[q_] = s.uy[p]; s.iuz[q_] = s.uz[p];
+            s.iw[q_] = s.w[p];
+            s.iid[q_] = s.id[p];
+            if constexpr (HAS_Z) s.izs[q_] = s.zs[p];
+        } else {
+            g.flags[FLAG_MIGRATE] = 1;
+        }
+    }
     __syncthreads();
 
     // ---- flush the current tile (guards overlap neighbouring supercells)
@@ -280,7 +376,7 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
         const int gi = gx + g.nx * (gy + g.ny * gz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long long iv = (long long)tJ[c][t];
+            const long long iv = (long long)tJ[c * T::JN + t];
             if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
         }
     }
@@ -293,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_push(GridView g, SpeciesView s, float js
 
 hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, hipStream_t st)
 {
+    if (s.cap > g.qcap) return hipErrorInvalidValue;  // the deposit queue must hold a full supercell
     const dim3 grid(g.nsc);
     const bool hz = s.zs != nullptr;
     // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30

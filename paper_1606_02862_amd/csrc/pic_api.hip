@@ -348,6 +348,13 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     for (int s = 0; s < n_species; ++s) {
         if ((rc = alloc_species(c, s))) return bail(rc);
     }
+    // one deposit queue shared by the species (their particle kernels run one after another)
+    g.qcap = 0;
+    for (int s = 0; s < n_species; ++s) g.qcap = std::max(g.qcap, c->sp[s].v.cap);
+    if (!(g.qbuf = (float*)dev_alloc(c, (size_t)7 * g.nsc * g.qcap * 4))) {
+        c->err = "device allocation of the deposit queue failed";
+        return bail(PIC_ERR_OOM);
+    }
     for (int s = 0; s < n_species; ++s) {
         Species& S = c->sp[s];
         const pic_species_t& d = S.desc;

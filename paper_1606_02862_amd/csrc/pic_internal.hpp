@@ -34,6 +34,8 @@ struct GridView {
     float* B;
     float* J;
     int32_t* flags;
+    float* qbuf;           // deposit queue: 7 arrays of nsc * qcap (x0,y0,z0,x1,y1,z1,qw)
+    int qcap;              // queue slots per supercell (>= every species' frame capacity)
 };
 
 struct SpeciesView {

@@ -194,6 +194,109 @@ typedef struct {
 } pic_timing_t;
 int pic_timing(pic_ctx* ctx, int enable, pic_timing_t* out);
 
+/* ------------------------------------------------------------------------
+ * Monte Carlo electron-impact ionisation (the Monte Carlo atomic-physics step
+ * the paper's introduction adds to the PIC cycle), single-shell Lotz model.
+ *
+ * For every ion species with z_max > 0 and ionize_into >= 0, per ion with
+ * Z < z_max:
+ *   - n_e and kT_e of the ion's cell from nearest-grid-point moments of the
+ *     electrons of species ionize_into (drift removed):
+ *       n_e = (sum w / dV) n_ref_cm3,  kT_e = m_e c^2 (sum w u^2 / sum w - |ubar|^2) / 3;
+ *   - rate nu = n_e <sigma v>, <sigma v> the Lotz cross-section
+ *     sigma(E) = a q ln(E/P) / (E P) (a = 4.5e-14 cm^2 eV^2, P = ionization_ev[Z],
+ *     q = lotz_q[Z]) averaged over a Maxwellian, evaluated as
+ *       vbar (a q / (P kT)) e^{-P/kT} sum_k w_k ln(1 + x_k kT / P)
+ *     with the 64-point Gauss-Laguerre rule (x_k, w_k) in FP64 (PIC_RATE_EXACT),
+ *     or by the learned surrogate (PIC_RATE_MLP, see below);
+ *   - p = 1 - exp(-nu dt / omega_p) with omega_p the plasma frequency of
+ *     n_ref_cm3; the ion ionises when the Philox uniform of counter
+ *     (id, species, 2, step) is below p: Z += 1 and an electron is born at the
+ *     ion's position with its momentum and weight, id
+ *       N0 + (ion id - first ion id) * z_max + (Z_new - 1)
+ *     (N0 = number of particles at t = 0), appended to the same supercell's
+ *     frames.  At most one event per ion per call.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t ions_active;   /* ions with Z < z_max at the start of the call */
+    int64_t ionized;       /* ionisation events */
+    int64_t fallback;      /* PIC_RATE_MLP: ions rated by the exact quadrature instead */
+    int64_t electrons;     /* particles of the receiving species after the call */
+    double rate_ms;        /* GPU time of the rate stage (HIP events, handle's stream) */
+    double total_ms;       /* GPU time of the whole call */
+} pic_ionize_stats_t;
+
+/* One ionisation step for every ionising species.  PIC_ERR_STATE if the
+ * handle has no ionising species, or for PIC_RATE_MLP before a surrogate was
+ * trained or loaded; PIC_ERR_CAPACITY if a supercell's electron frames are full
+ * (ions whose electron does not fit are left unchanged). */
+int pic_ionize(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* out);
+
+/* Per-cell n_e (cm^-3) and kT_e (eV) of the electrons that species `species`
+ * ionises into, as used by pic_ionize (computed now).  Host arrays of
+ * nx*ny*nz doubles, cell index i + nx (j + ny k); either may be NULL. */
+int pic_cell_moments(pic_ctx* ctx, int species, double* ne_cm3, double* kT_ev);
+
+/* ln nu (nu in 1/s) for n host samples (kT_e eV, n_e cm^-3, charge state Z of
+ * species `species`), by the exact quadrature or the surrogate (with its
+ * exact fallback outside the trained range).  Synchronous. */
+int pic_rate_eval(pic_ctx* ctx, pic_rate_mode_t mode, int species, int64_t n, const double* kT_ev,
+                  const double* ne_cm3, const int32_t* Z, double* ln_rate);
+
+/* The library's 64-point Gauss-Laguerre rule (weight e^{-x} on [0, inf)),
+ * computed on the host at load time by the Golub-Welsch eigenvalue method
+ * and refined by Newton steps on the Laguerre recurrence.  Needs no GPU. */
+int pic_gauss_laguerre64(double* nodes, double* weights);
+
+/* ------------------------------------------------------------------------
+ * Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1, SiLU activations.
+ *   inputs  (log10 kT_e - 2)/2, (log10 n_e - 21)/2, one-hot of Z (6 states);
+ *   output  ln nu = ln nu_prior + mu + s * y, where ln nu_prior is the rate
+ *           with e^z E1(z) (z = P/kT) replaced by ln(1 + 1/z):
+ *           ln(n_e vbar a q / (P kT)) - z + ln ln(1 + 1/z).
+ * Inference runs as a fused BF16-MFMA kernel (BF16 weights and activations,
+ * FP32 accumulation and epilogue); inputs outside the trained range
+ * [t_min, t_max] x [n_min, n_max] take the exact quadrature.
+ * Parameters, flat FP32 (PIC_MLP_NPARAM): W1[64][8], b1[64], W2[64][64],
+ * b2[64], W3[1][64], b3[1] (row-major [out][in]).
+ * ------------------------------------------------------------------------ */
+#define PIC_MLP_NPARAM 4801
+
+typedef struct {
+    int64_t n_train;       /* training samples (exact labels generated on the GPU) */
+    int32_t batch;         /* minibatch size (multiple of 64) */
+    int32_t steps;         /* Adam steps */
+    double lr;             /* initial learning rate (cosine decay to lr_final) */
+    double lr_final;
+    uint64_t seed;         /* Philox key of sample generation, batch draws and init */
+    double t_min_ev, t_max_ev, n_min_cm3, n_max_cm3;  /* log-uniform sampling ranges */
+} pic_mlp_train_cfg_t;
+
+typedef struct {
+    double loss_first;     /* minibatch loss of the first step */
+    double loss_last;      /* mean minibatch loss of the last 100 steps */
+    double mu, s;          /* target standardisation */
+    double train_ms;       /* GPU time of data generation + training */
+    int64_t steps;
+} pic_mlp_report_t;
+
+/* Generate n_train exact-labelled samples on the GPU and train the surrogate of
+ * ion species `species` with the library's own forward / backward (BF16 MFMA,
+ * FP32 accumulation) and Adam (FP32 master weights) kernels. */
+int pic_mlp_train(pic_ctx* ctx, int species, const pic_mlp_train_cfg_t* cfg, pic_mlp_report_t* out);
+
+/* Copy the FP32 master parameters (PIC_MLP_NPARAM floats) and (mu, s) out /
+ * in.  set also defines the trained range (t/n min/max, 4 doubles). */
+int pic_mlp_get_params(pic_ctx* ctx, int species, float* params, double* mu_s, double* range);
+int pic_mlp_set_params(pic_ctx* ctx, int species, const float* params, const double* mu_s, const double* range);
+
+/* One forward + backward pass of the training kernels on n host samples
+ * (features X[n][8], targets t[n]) with the current parameters: writes the
+ * mean squared error and its gradient (PIC_MLP_NPARAM floats).  n must be a
+ * multiple of 64.  Synchronous. */
+int pic_mlp_loss_grad(pic_ctx* ctx, int species, int64_t n, const float* X, const float* t, double* loss,
+                      float* grad);
+
 /* Release every device buffer of the handle.  NULL is accepted. */
 int pic_destroy(pic_ctx* ctx);
 

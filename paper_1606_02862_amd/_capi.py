@@ -57,6 +57,29 @@ class TimingT(C.Structure):
                 ("push_launches", C.c_int64), ("push_particles", C.c_int64)]
 
 
+class IonizeStatsT(C.Structure):
+    _fields_ = [("ions_active", C.c_int64), ("ionized", C.c_int64), ("fallback", C.c_int64),
+                ("electrons", C.c_int64), ("rate_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+class MlpTrainCfgT(C.Structure):
+    _fields_ = [("n_train", C.c_int64), ("batch", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("seed", C.c_uint64), ("t_min_ev", C.c_double), ("t_max_ev", C.c_double),
+                ("n_min_cm3", C.c_double), ("n_max_cm3", C.c_double)]
+
+
+class MlpReportT(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("mu", C.c_double), ("s", C.c_double),
+                ("train_ms", C.c_double), ("steps", C.c_int64)]
+
+
+PIC_MLP_NPARAM = 4801
+PIC_RATE_EXACT, PIC_RATE_MLP = 0, 1
+
+_DP = C.POINTER(C.c_double)
+_FP = C.POINTER(C.c_float)
+_IP = C.POINTER(C.c_int32)
+
 # name -> (restype, argtypes); every symbol the header declares
 SIGNATURES = {
     "pic_abi_version": (C.c_int, []),
@@ -71,6 +94,14 @@ SIGNATURES = {
     "pic_set_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pic_mark_reference": (C.c_int, [C.c_void_p]),
     "pic_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TimingT)]),
+    "pic_ionize": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IonizeStatsT)]),
+    "pic_cell_moments": (C.c_int, [C.c_void_p, C.c_int, _DP, _DP]),
+    "pic_rate_eval": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),
+    "pic_gauss_laguerre64": (C.c_int, [_DP, _DP]),
+    "pic_mlp_train": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(MlpTrainCfgT), C.POINTER(MlpReportT)]),
+    "pic_mlp_get_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP]),
+    "pic_mlp_set_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP]),
+    "pic_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _FP, _FP, _DP, _FP]),
     "pic_destroy": (C.c_int, [C.c_void_p]),
     "pic_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -1,0 +1,594 @@
+// Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1 network with SiLU,
+// BF16 weights and activations on the matrix cores, FP32 accumulation.
+//
+// Wave tiling: a wave evaluates 16 samples at a time.  Lane l works on sample
+// l % 16 for layer 1 and on hidden units 8*(l/16) + j (+32) so that its
+// activations are directly the A operand of v_mfma_f32_16x16x32_bf16
+// (A[i][k]: lane i + 16*(k/8) holds k % 8); layer 2 is 2 K-steps x 4 N-tiles
+// = 8 MFMAs with W2 held in registers as the B operand; the result tile
+// (D[i][n]: lane n%16 + 16*(i/4) holds i % 4) gets b2 + SiLU and the dot
+// with W3 as per-lane partial sums reduced over the 16 lanes of a row group.
+// Layer 1 (2 continuous inputs + one-hot charge state) is a VALU column
+// gather; the prior and the exact fallback are an FP32 / FP64 epilogue.
+//
+// Training uses the same forward plus a backward pass per 16-sample tile:
+// dW2 = dZ2^T H1 and dH1 = dZ2 W2 on MFMA (16x16x16 over the samples and
+// 16x16x32 over the hidden units), the small layers on VALU; gradients are
+// summed per wave in registers / LDS and added to a global accumulator once
+// per wave; Adam updates FP32 master weights.
+#include "pic_device.hpp"
+
+namespace pic {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int NH = 64, NIN = 8;
+constexpr int OFF_W1 = 0, OFF_B1 = NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
+              OFF_B3 = OFF_W3 + NH, NPARAM = OFF_B3 + 1;
+static_assert(NPARAM == PIC_MLP_NPARAM, "parameter count");
+
+__device__ inline float bf16r(float x) { return (float)(__bf16)x; }
+__device__ inline float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigm(z); }
+__device__ inline float dsilu(float z)
+{
+    const float s = sigm(z);
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ln nu_prior = ln(n_e vbar a q / (P kT)) - z + ln ln(1 + 1/z), z = P / kT (FP32)
+__device__ inline float ln_prior(float kT, float ne, float P, float q)
+{
+    const float z = P / kT;
+    const float vbar = (float)C_CM_S * sqrtf(8.0f * kT / ((float)M_PI * (float)ME_C2_EV));
+    return logf(ne) + logf(vbar) + logf((float)LOTZ_A * q / (P * kT)) - z + logf(log1pf(1.0f / z));
+}
+
+// The 8 parameters of one network slice a lane needs for a forward tile.
+struct LaneWeights {
+    bf16x8 w2[4][2];   // B operands: W2[16t + l%16][32s + 8(l/16) + j]
+    float b2[4], w3[4];
+};
+
+__device__ inline void load_lane_weights(const float* P, int lane, LaneWeights& lw)
+{
+    const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) lw.w2[t][s][j] = (__bf16)P[OFF_W2 + (16 * t + c) * NH + 32 * s + 8 * g + j];
+        lw.b2[t] = P[OFF_B2 + 16 * t + c];
+        lw.w3[t] = bf16r(P[OFF_W3 + 16 * t + c]);
+    }
+}
+
+// Layer 1 column table in LDS: c1[z][k] = W1[k][2+z] + b1[k] (z < 6), and the
+// two continuous columns, all BF16-rounded weights.
+struct L1Table {
+    float wx0[NH], wx1[NH], cz[6][NH];
+};
+
+__device__ inline void fill_l1(const float* P, L1Table& T)
+{
+    for (int k = threadIdx.x; k < NH; k += blockDim.x) {
+        T.wx0[k] = bf16r(P[OFF_W1 + k * NIN + 0]);
+        T.wx1[k] = bf16r(P[OFF_W1 + k * NIN + 1]);
+        for (int z = 0; z < 6; ++z) T.cz[z][k] = bf16r(P[OFF_W1 + k * NIN + 2 + z]) + P[OFF_B1 + k];
+    }
+}
+
+// Forward of 16 samples held by the wave: lane l supplies sample l%16's
+// (x0, x1, z).  Returns y for sample (4*(l/16) + r) in out[r] (all lanes of a
+// row group hold the same four values).
+__device__ inline void forward_tile(const L1Table& T, const LaneWeights& lw, float b3, int lane, float x0, float x1, int z,
+                                    float out[4])
+{
+    const int g = lane >> 4;
+    bf16x8 a[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * s + 8 * g + j;
+            const float zz = fmaf(T.wx0[k], x0, fmaf(T.wx1[k], x1, T.cz[z][k]));
+            a[s][j] = (__bf16)silu(zz);
+        }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        floatx4 d = {0.f, 0.f, 0.f, 0.f};
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], lw.w2[t][0], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], lw.w2[t][1], d, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = fmaf(lw.w3[t], bf16r(silu(d[r] + lw.b2[t])), acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float v = acc[r];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        out[r] = v + b3;
+    }
+}
+
+// ---------------------------------------------------------------- inference
+struct MlpArgs {
+    const float* params;
+    float mu, s;
+    float t_min, t_max, n_min, n_max;  // trained range (eV, cm^-3)
+};
+
+__device__ inline float x0_of(float kT) { return (log10f(kT) - 2.0f) * 0.5f; }
+__device__ inline float x1_of(float ne) { return (log10f(ne) - 21.0f) * 0.5f; }
+
+// Per supercell of ions: nu[p] for every ion (0 for Z >= z_max); out-of-range
+// inputs take the exact FP64 quadrature.  counters[0] += active ions,
+// counters[2] += fallbacks.
+__global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion, IonTables tab, MlpArgs m,
+                                                    const double* ne, const double* kT, double* nu, const double* gl,
+                                                    unsigned long long* counters)
+{
+    __shared__ L1Table T;
+    __shared__ double glx[GL_NODES], glw[GL_NODES];
+    __shared__ int s_active, s_fallback;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    fill_l1(m.params, T);
+    if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
+    if (tid == 0) { s_active = 0; s_fallback = 0; }
+    LaneWeights lw;
+    load_lane_weights(m.params, lane, lw);
+    const float b3 = m.params[OFF_B3];
+    __syncthreads();
+    const int sc = blockIdx.x;
+    const int n = ion.count[sc];
+    const int64_t base = (int64_t)sc * ion.cap;
+    const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
+    int active = 0, fallback = 0;
+    const int ntile = (n + 15) / 16;
+    for (int tile = wave; tile < ntile; tile += BLOCK / 64) {
+        // lane l%16 reads sample 16*tile + l%16 (every row group reads the same 16)
+        const int t = 16 * tile + (lane & 15);
+        float x0 = 0.f, x1 = 0.f, fkT = 1.f, fne = 1.f;
+        int Z = 0;
+        bool act = false, inr = false;
+        double dkT = 0.0, dne = 0.0;
+        int64_t p = 0;
+        if (t < n) {
+            p = base + t;
+            Z = ion.zs[p];
+            act = Z < tab.z_max;
+            const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
+                               (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
+            dkT = kT[gi];
+            dne = ne[gi];
+            fkT = (float)dkT;
+            fne = (float)dne;
+            inr = act && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min && fne <= m.n_max;
+            if (inr) { x0 = x0_of(fkT); x1 = x1_of(fne); }
+        }
+        float y[4];
+        forward_tile(T, lw, b3, lane, x0, x1, inr ? Z : 0, y);
+        // lane l (< 16) finishes sample 16*tile + l: its y lives in row group l/4, slot l%4
+        const int src = 16 * (lane >> 2);
+        float yv = __shfl(y[0], src, 64), y1v = __shfl(y[1], src, 64), y2v = __shfl(y[2], src, 64),
+              y3v = __shfl(y[3], src, 64);
+        const int r = lane & 3;
+        const float ys = r == 0 ? yv : (r == 1 ? y1v : (r == 2 ? y2v : y3v));
+        if (lane < 16 && t < n) {
+            double v = 0.0;
+            if (act) {
+                ++active;
+                if (inr) {
+                    const float lnv = ln_prior(fkT, fne, (float)tab.P[Z], (float)tab.q[Z]) + m.mu + m.s * ys;
+                    v = exp((double)lnv);
+                } else {
+                    ++fallback;
+                    v = rate_exact(dkT, dne, tab.P[Z], tab.q[Z], glx, glw);
+                }
+            }
+            nu[p] = v;
+        }
+    }
+    atomicAdd(&s_active, active);
+    atomicAdd(&s_fallback, fallback);
+    __syncthreads();
+    if (tid == 0) {
+        if (s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
+        if (s_fallback) atomicAdd(&counters[2], (unsigned long long)s_fallback);
+    }
+}
+
+hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,
+                           const double* ne, const double* kT, double* nu, const double* gl,
+                           unsigned long long* counters, hipStream_t st)
+{
+    MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
+    hipLaunchKernelGGL(k_rate_mlp, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, gl, counters);
+    return hipGetLastError();
+}
+
+// ln nu of independent samples by the surrogate (exact fallback outside range).
+__global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Zs,
+                                                       IonTables tab, MlpArgs m, const double* gl, double* out)
+{
+    __shared__ L1Table T;
+    __shared__ double glx[GL_NODES], glw[GL_NODES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    fill_l1(m.params, T);
+    if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
+    LaneWeights lw;
+    load_lane_weights(m.params, lane, lw);
+    const float b3 = m.params[OFF_B3];
+    __syncthreads();
+    const int64_t ntile = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * (BLOCK / 64) + wave; tile < ntile; tile += (int64_t)gridDim.x * (BLOCK / 64)) {
+        const int64_t i = 16 * tile + (lane & 15);
+        float x0 = 0.f, x1 = 0.f, fkT = 1.f, fne = 1.f;
+        int Z = 0;
+        bool inr = false;
+        if (i < n) {
+            Z = Zs[i];
+            fkT = (float)kT[i];
+            fne = (float)ne[i];
+            inr = Z >= 0 && Z < tab.z_max && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min &&
+                  fne <= m.n_max;
+            if (inr) { x0 = x0_of(fkT); x1 = x1_of(fne); }
+        }
+        float y[4];
+        forward_tile(T, lw, b3, lane, x0, x1, inr ? Z : 0, y);
+        const int src = 16 * (lane >> 2);
+        float yv = __shfl(y[0], src, 64), y1v = __shfl(y[1], src, 64), y2v = __shfl(y[2], src, 64),
+              y3v = __shfl(y[3], src, 64);
+        const int r = lane & 3;
+        const float ys = r == 0 ? yv : (r == 1 ? y1v : (r == 2 ? y2v : y3v));
+        if (lane < 16 && i < n) {
+            if (inr) {
+                out[i] = (double)(ln_prior(fkT, fne, (float)tab.P[Z], (float)tab.q[Z]) + m.mu + m.s * ys);
+            } else if (Z >= 0 && Z < tab.z_max) {
+                const double v = rate_exact(kT[i], ne[i], tab.P[Z], tab.q[Z], glx, glw);
+                out[i] = v > 0.0 ? log(v) : -INFINITY;
+            } else {
+                out[i] = -INFINITY;
+            }
+        }
+    }
+}
+
+hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
+                              const MlpLaunch& ml, const double* gl, double* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
+    int64_t blocks = (n + 16 * (BLOCK / 64) - 1) / (16 * (BLOCK / 64));
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_ln_rate_mlp, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, kT, ne, Z, tab, m, gl, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- training data
+// Sample i: Philox (i, 0, 3, 0) -> log-uniform kT and n_e, Z uniform in 0..5;
+// features (x0, x1, one-hot Z) and the exact residual target
+// r = ln nu_exact - ln nu_prior (FP64; the prior here in FP64 too).
+__global__ __launch_bounds__(BLOCK) void k_mlp_gen(int64_t n, uint64_t seed, MlpGen a, IonTables tab, const double* gl,
+                                                   float* X, double* r)
+{
+    __shared__ double glx[GL_NODES], glw[GL_NODES];
+    if (threadIdx.x < GL_NODES) { glx[threadIdx.x] = gl[threadIdx.x]; glw[threadIdx.x] = gl[GL_NODES + threadIdx.x]; }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const Philox4 u = philox4x64_10((uint64_t)i, 0, PURPOSE_MLP_DATA, 0, seed, 0);
+    const double lt = a.lt_min + (a.lt_max - a.lt_min) * u01(u.v[0]);
+    const double ln10n = a.ln_min + (a.ln_max - a.ln_min) * u01(u.v[1]);
+    int Z = (int)(u01(u.v[2]) * 6.0);
+    Z = Z > 5 ? 5 : Z;
+    const double kT = pow(10.0, lt), ne = pow(10.0, ln10n);
+    float* x = X + i * NIN;
+    x[0] = (float)((lt - 2.0) * 0.5);
+    x[1] = (float)((ln10n - 21.0) * 0.5);
+    for (int k = 0; k < 6; ++k) x[2 + k] = (k == Z) ? 1.0f : 0.0f;
+    const double P = tab.P[Z], q = tab.q[Z];
+    const double z = P / kT;
+    const double prior = log(ne * vbar_cm_s(kT) * LOTZ_A * q / (P * kT)) - z + log(log1p(1.0 / z));
+    r[i] = ln_rate_exact(kT, ne, P, q, glx, glw) - prior;
+}
+
+hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTables& tab, const double* gl, float* X,
+                          double* r, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_gen, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, n, seed, a, tab, gl, X,
+                       r);
+    return hipGetLastError();
+}
+
+// Mean and standard deviation of r (two passes, FP64): partial sums per block,
+// then one block finishes; target t = (r - mu) / s written as FP32.
+__global__ __launch_bounds__(BLOCK) void k_mlp_moments(int64_t n, const double* r, double* partial)
+{
+    __shared__ double sa[BLOCK / 64], sb[BLOCK / 64];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        a += r[i];
+        b += r[i] * r[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_xor(a, o, 64); b += __shfl_xor(b, o, 64); }
+    if ((threadIdx.x & 63) == 0) { sa[threadIdx.x >> 6] = a; sb[threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) { ta += sa[w]; tb += sb[w]; }
+        partial[2 * blockIdx.x] = ta;
+        partial[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void k_mlp_moments_final(int64_t n, int nb, const double* partial, double* mu_s)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nb; ++i) { a += partial[2 * i]; b += partial[2 * i + 1]; }
+    const double mu = a / (double)n;
+    double var = b / (double)n - mu * mu;
+    var = var > 1e-300 ? var : 1e-300;
+    mu_s[0] = mu;
+    mu_s[1] = sqrt(var);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_mlp_targets(int64_t n, const double* r, const double* mu_s, float* t)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) t[i] = (float)((r[i] - mu_s[0]) / mu_s[1]);
+}
+
+hipError_t launch_mlp_standardize(int64_t n, const double* r, double* partial, double* mu_s, float* t, hipStream_t st)
+{
+    const int nb = 512;
+    hipLaunchKernelGGL(k_mlp_moments, dim3(nb), dim3(BLOCK), 0, st, n, r, partial);
+    hipLaunchKernelGGL(k_mlp_moments_final, dim3(1), dim3(64), 0, st, n, nb, partial, mu_s);
+    hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, n, r, mu_s, t);
+    return hipGetLastError();
+}
+
+// Initial weights: uniform(-1,1) * sqrt(3 / fan_in) from Philox (p, 0, 5, 0); biases 0.
+__global__ void k_mlp_init(uint64_t seed, float* P, float* adam_m, float* adam_v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const Philox4 u = philox4x64_10((uint64_t)i, 0, PURPOSE_MLP_INIT, 0, seed, 0);
+    const double v = 2.0 * u01(u.v[0]) - 1.0;
+    float w = 0.0f;
+    if (i < OFF_B1) w = (float)(v * sqrt(3.0 / NIN));
+    else if (i >= OFF_W2 && i < OFF_B2) w = (float)(v * sqrt(3.0 / NH));
+    else if (i >= OFF_W3 && i < OFF_B3) w = (float)(v * sqrt(3.0 / NH));
+    P[i] = w;
+    adam_m[i] = 0.0f;
+    adam_v[i] = 0.0f;
+}
+
+hipError_t launch_mlp_init(uint64_t seed, float* P, float* m, float* v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_init, dim3((NPARAM + 255) / 256), dim3(256), 0, st, seed, P, m, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- training step
+// Forward + backward of a minibatch.  Sample slot b of the batch is training
+// sample idx[b] (explicit list) or, with idx == nullptr and draw_seed != 0,
+// Philox (b, step, 4, 0) mod n_data.  Every wave takes 16-sample tiles; grad
+// (NPARAM floats) and loss (sum of squared errors) accumulate atomically.
+struct StepArgs {
+    const float* X;      // [n_data][8]
+    const float* t;      // [n_data]
+    int64_t n_data;
+    int batch;
+    uint64_t draw_seed;
+    int64_t step;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, float* grad, double* loss)
+{
+    __shared__ float sW2[NH][NH + 1];                 // W2 (bf16-rounded), [out][in]
+    __shared__ float sW1[NH][NIN], sB1[NH], sW3[NH];
+    __shared__ float h1t[BLOCK / 64][16][NH + 1];      // per-wave H1 tile [sample][k]
+    __shared__ float dz2t[BLOCK / 64][16][NH + 1];     // per-wave dZ2 tile [sample][n]
+    __shared__ float gW1[BLOCK / 64][NH][NIN + 1];     // per-wave dW1 | db1
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    for (int i = tid; i < NH * NH; i += BLOCK) sW2[i / NH][i % NH] = bf16r(P[OFF_W2 + i]);
+    for (int i = tid; i < NH * NIN; i += BLOCK) sW1[i / NIN][i % NIN] = bf16r(P[OFF_W1 + i]);
+    for (int i = tid; i < NH; i += BLOCK) { sB1[i] = P[OFF_B1 + i]; sW3[i] = bf16r(P[OFF_W3 + i]); }
+    for (int i = lane; i < NH * (NIN + 1); i += 64) gW1[wave][i / (NIN + 1)][i % (NIN + 1)] = 0.0f;
+    __syncthreads();
+    const float b3 = P[OFF_B3];
+    float b2v[4];
+    for (int t = 0; t < 4; ++t) b2v[t] = P[OFF_B2 + 16 * t + c];
+
+    floatx4 accW2[4][4];  // dW2 tiles [n-tile][k-tile]
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) accW2[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float gW3[4] = {0.f, 0.f, 0.f, 0.f}, gB2[4] = {0.f, 0.f, 0.f, 0.f}, gB3 = 0.f;
+    double lsum = 0.0;
+    const float inv_b = 1.0f / (float)a.batch;
+
+    auto sample = [&](int b) -> int64_t {
+        if (a.draw_seed == 0) return b;
+        const Philox4 u = philox4x64_10((uint64_t)b, (uint64_t)a.step, PURPOSE_MLP_BATCH, 0, a.draw_seed, 0);
+        return (int64_t)(u.v[0] % (uint64_t)a.n_data);
+    };
+    const int ntile = a.batch / 16;
+    const int nwave = gridDim.x * (BLOCK / 64);
+    // every wave of the block runs the same number of rounds (barriers inside)
+    for (int round = blockIdx.x * (BLOCK / 64); round < ntile; round += nwave) {
+        const int tile = round + wave;
+        const bool valid = tile < ntile;
+        bf16x8 h1[2];
+        float z2[4][4], dy[4];
+        if (valid) {
+            const int64_t si = sample(16 * tile + c);
+            float x[NIN];
+            for (int k = 0; k < NIN; ++k) x[k] = a.X[si * NIN + k];
+            // layer 1 for hidden units 32s + 8g + j of sample c
+            for (int s = 0; s < 2; ++s)
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 32 * s + 8 * g + j;
+                    float z = sB1[k];
+                    for (int q = 0; q < NIN; ++q) z = fmaf(sW1[k][q], x[q], z);
+                    const float h = bf16r(silu(z));
+                    h1[s][j] = (__bf16)h;
+                    h1t[wave][c][k] = h;
+                }
+            // layer 2 + head: rows i = 4g + r, columns n = 16t + c
+            float y[4] = {0.f, 0.f, 0.f, 0.f};
+            for (int t = 0; t < 4; ++t) {
+                bf16x8 w[2];
+                for (int s = 0; s < 2; ++s)
+                    for (int j = 0; j < 8; ++j) w[s][j] = (__bf16)sW2[16 * t + c][32 * s + 8 * g + j];
+                floatx4 d = {0.f, 0.f, 0.f, 0.f};
+                d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1[0], w[0], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1[1], w[1], d, 0, 0, 0);
+                for (int r = 0; r < 4; ++r) {
+                    z2[t][r] = d[r] + b2v[t];
+                    y[r] = fmaf(sW3[16 * t + c], bf16r(silu(z2[t][r])), y[r]);
+                }
+            }
+            for (int r = 0; r < 4; ++r) {
+                float v = y[r];
+                v += __shfl_xor(v, 1, 64);
+                v += __shfl_xor(v, 2, 64);
+                v += __shfl_xor(v, 4, 64);
+                v += __shfl_xor(v, 8, 64);
+                const int64_t so = sample(16 * tile + 4 * g + r);
+                const float res = v + b3 - a.t[so];
+                dy[r] = 2.0f * res * inv_b;
+                if (c == 0) lsum += (double)res * res;
+            }
+            // head and layer-2 backward: dZ2[i][n] = dy_i W3[n] silu'(z2)
+            for (int t = 0; t < 4; ++t)
+                for (int r = 0; r < 4; ++r) {
+                    const float h2 = bf16r(silu(z2[t][r]));
+                    gW3[t] = fmaf(dy[r], h2, gW3[t]);
+                    const float dz = dy[r] * sW3[16 * t + c] * dsilu(z2[t][r]);
+                    gB2[t] += dz;
+                    dz2t[wave][4 * g + r][16 * t + c] = dz;
+                }
+            for (int r = 0; r < 4; ++r) gB3 += (c == 0) ? dy[r] : 0.0f;
+        }
+        __syncthreads();  // h1t / dz2t of this round complete
+        if (valid) {
+            // dW2[n][k] += sum_i dZ2[i][n] H1[i][k]: 16x16x16 MFMA, K = the 16 samples
+            for (int tn = 0; tn < 4; ++tn) {
+                bf16x4 A;
+                for (int j = 0; j < 4; ++j) A[j] = (__bf16)dz2t[wave][4 * g + j][16 * tn + c];
+                for (int tk = 0; tk < 4; ++tk) {
+                    bf16x4 Bv;
+                    for (int j = 0; j < 4; ++j) Bv[j] = (__bf16)h1t[wave][4 * g + j][16 * tk + c];
+                    accW2[tn][tk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv, accW2[tn][tk], 0, 0, 0);
+                }
+            }
+            // dH1[i][k] = sum_n dZ2[i][n] W2[n][k]: 16x16x32 MFMA over n; rows 4g + r, column 16tk + c
+            bf16x8 dA[2];
+            for (int s = 0; s < 2; ++s)
+                for (int j = 0; j < 8; ++j) dA[s][j] = (__bf16)dz2t[wave][c][32 * s + 8 * g + j];
+            for (int tk = 0; tk < 4; ++tk) {
+                bf16x8 Bv[2];
+                for (int s = 0; s < 2; ++s)
+                    for (int j = 0; j < 8; ++j) Bv[s][j] = (__bf16)sW2[32 * s + 8 * g + j][16 * tk + c];
+                floatx4 d = {0.f, 0.f, 0.f, 0.f};
+                d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[0], Bv[0], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[1], Bv[1], d, 0, 0, 0);
+                // dZ1 = dH1 silu'(z1) for samples 4g + r at unit k; dW1 / db1 partials
+                const int k = 16 * tk + c;
+                float part[NIN + 1];
+                for (int q = 0; q <= NIN; ++q) part[q] = 0.0f;
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t so = sample(16 * tile + 4 * g + r);
+                    float xs[NIN];
+                    for (int q = 0; q < NIN; ++q) xs[q] = a.X[so * NIN + q];
+                    float z1 = sB1[k];
+                    for (int q = 0; q < NIN; ++q) z1 = fmaf(sW1[k][q], xs[q], z1);
+                    const float dz1 = d[r] * dsilu(z1);
+                    for (int q = 0; q < NIN; ++q) part[q] = fmaf(dz1, xs[q], part[q]);
+                    part[NIN] += dz1;
+                }
+                // sum over the four row groups (lanes c, c+16, c+32, c+48); lane c owns the entry
+                for (int q = 0; q <= NIN; ++q) {
+                    float v = part[q];
+                    v += __shfl_xor(v, 16, 64);
+                    v += __shfl_xor(v, 32, 64);
+                    if (g == 0) gW1[wave][k][q] += v;
+                }
+            }
+        }
+        __syncthreads();  // the next round overwrites h1t / dz2t
+    }
+    // ---- wave partials to the global accumulator
+    for (int tn = 0; tn < 4; ++tn)
+        for (int tk = 0; tk < 4; ++tk)
+            for (int r = 0; r < 4; ++r) {
+                // D[m = n][nn = k]: row 16tn + 4g + r, column 16tk + c
+                const int n = 16 * tn + 4 * g + r, k = 16 * tk + c;
+                unsafeAtomicAdd(&grad[OFF_W2 + n * NH + k], accW2[tn][tk][r]);
+            }
+    for (int t = 0; t < 4; ++t) {
+        float v = gW3[t], w = gB2[t];
+        v += __shfl_xor(v, 16, 64); v += __shfl_xor(v, 32, 64);
+        w += __shfl_xor(w, 16, 64); w += __shfl_xor(w, 32, 64);
+        if (g == 0) {
+            unsafeAtomicAdd(&grad[OFF_W3 + 16 * t + c], v);
+            unsafeAtomicAdd(&grad[OFF_B2 + 16 * t + c], w);
+        }
+    }
+    {
+        float v = gB3;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) unsafeAtomicAdd(&grad[OFF_B3], v);
+        double l = lsum;
+        for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+        if (lane == 0) unsafeAtomicAdd(loss, l);
+    }
+    for (int i = lane; i < NH * (NIN + 1); i += 64) {
+        const int k = i / (NIN + 1), q = i % (NIN + 1);
+        const float v = gW1[wave][k][q];
+        if (q < NIN) unsafeAtomicAdd(&grad[OFF_W1 + k * NIN + q], v);
+        else unsafeAtomicAdd(&grad[OFF_B1 + k], v);
+    }
+}
+
+hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double* loss, hipStream_t st)
+{
+    StepArgs a{s.X, s.t, s.n_data, s.batch, s.draw_seed, s.step};
+    int blocks = s.batch / 16 / (BLOCK / 64);
+    if (blocks > 64) blocks = 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_mlp_step, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
+    return hipGetLastError();
+}
+
+// Adam on the FP32 master weights (beta1 0.9, beta2 0.999, eps 1e-8), then
+// clears the gradient accumulator.
+__global__ void k_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const float gi = grad[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    P[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+    grad[i] = 0.0f;
+}
+
+hipError_t launch_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, grad, m, v, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -36,6 +36,23 @@ struct pic_ctx {
     int ev_used = 0;
     int64_t pending_particles = 0;
     int pending_launches = 0;
+    // ionisation
+    double* gl = nullptr;                    // 64 nodes then 64 weights
+    double* ne = nullptr;                    // per-cell n_e (cm^-3)
+    double* kT = nullptr;                    // per-cell kT_e (eV)
+    double* nu[PIC_MAX_SPECIES] = {};        // per ion slot rate (1/s)
+    unsigned long long* counters = nullptr;  // active, ionised, fallback
+    hipEvent_t iev[4] = {};
+    // surrogate per ion species
+    struct Mlp {
+        float* params = nullptr;
+        float* m = nullptr;
+        float* v = nullptr;
+        float* grad = nullptr;
+        double mu = 0.0, s = 1.0;
+        double t_min = 1.0, t_max = 1e4, n_min = 1e19, n_max = 1e23;
+        bool ready = false;
+    } mlp[PIC_MAX_SPECIES];
 };
 
 static thread_local std::string g_init_error;
@@ -75,6 +92,19 @@ void* dev_alloc(pic_ctx* c, size_t bytes)
     return p;
 }
 
+void dev_free(pic_ctx* c, void* p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < c->owned.size(); ++i)
+        if (c->owned[i] == p) {
+            c->owned[i] = c->owned.back();
+            c->owned.pop_back();
+            break;
+        }
+    if (c->use_cb) c->alloc.free(p, c->alloc.user);
+    else (void)hipFree(p);
+}
+
 void release_all(pic_ctx* c)
 {
     for (void* p : c->owned) {
@@ -84,6 +114,8 @@ void release_all(pic_ctx* c)
     c->owned.clear();
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
+    for (hipEvent_t& e : c->iev)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
     if (c->flags_host) (void)hipHostFree(c->flags_host);
     c->flags_host = nullptr;
 }
@@ -187,6 +219,65 @@ int alloc_species(pic_ctx* c, int s)
     HIPCHK(c, launch_zero_i32(v.in_count, nsc, c->stream));
     HIPCHK(c, launch_zero_i32(v.hole_count, nsc, c->stream));
     return PIC_OK;
+}
+
+bool ionising(const pic_ctx* c, int s)
+{
+    return c->sp[s].desc.z_max > 0 && c->sp[s].desc.ionize_into >= 0;
+}
+
+int alloc_ionisation(pic_ctx* c)
+{
+    bool any = false;
+    for (int s = 0; s < c->nsp; ++s) any = any || (c->sp[s].desc.z_max > 0);
+    if (!any) return PIC_OK;
+    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    if (!(c->gl = (double*)dev_alloc(c, 2 * GL_NODES * 8)) || !(c->ne = (double*)dev_alloc(c, N * 8)) ||
+        !(c->kT = (double*)dev_alloc(c, N * 8)) || !(c->counters = (unsigned long long*)dev_alloc(c, 64)))
+        return fail(c, PIC_ERR_OOM, "device allocation of ionisation buffers failed");
+    for (int s = 0; s < c->nsp; ++s) {
+        if (c->sp[s].desc.z_max == 0) continue;
+        if (!(c->nu[s] = (double*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)))
+            return fail(c, PIC_ERR_OOM, "device allocation of ionisation rates failed");
+        pic_ctx::Mlp& m = c->mlp[s];
+        if (!(m.params = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.m = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) ||
+            !(m.v = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.grad = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)))
+            return fail(c, PIC_ERR_OOM, "device allocation of the surrogate failed");
+        HIPCHK(c, launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream));
+    }
+    const double* w;
+    const double* x = gauss_laguerre_nodes(&w);
+    double rule[2 * GL_NODES];
+    for (int k = 0; k < GL_NODES; ++k) { rule[k] = x[k]; rule[GL_NODES + k] = w[k]; }
+    HIPCHK(c, hipMemcpyAsync(c->gl, rule, sizeof rule, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (hipEvent_t& e : c->iev) HIPCHK(c, hipEventCreate(&e));
+    return PIC_OK;
+}
+
+IonTables ion_tables(const pic_ctx* c, int s)
+{
+    IonTables t{};
+    const pic_species_t& d = c->sp[s].desc;
+    for (int z = 0; z < PIC_MAX_ZSTATES; ++z) {
+        t.P[z] = z < d.z_max ? d.ionization_ev[z] : 1.0;
+        t.q[z] = z < d.z_max ? (double)d.lotz_q[z] : 0.0;
+    }
+    t.z_max = d.z_max;
+    return t;
+}
+
+MlpLaunch mlp_launch(const pic_ctx* c, int s)
+{
+    const pic_ctx::Mlp& m = c->mlp[s];
+    return MlpLaunch{m.params, m.mu, m.s, m.t_min, m.t_max, m.n_min, m.n_max};
+}
+
+// Plasma frequency (1/s) of the reference density, SI.
+double omega_p(double n_ref_cm3)
+{
+    const double e = 1.602176634e-19, eps0 = 8.8541878128e-12, me = 9.1093837015e-31;
+    return std::sqrt(n_ref_cm3 * 1e6 * e * e / (eps0 * me));
 }
 
 int read_flags(pic_ctx* c)
@@ -355,6 +446,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         c->err = "device allocation of the deposit queue failed";
         return bail(PIC_ERR_OOM);
     }
+    if ((rc = alloc_ionisation(c))) return bail(rc);
     for (int s = 0; s < n_species; ++s) {
         Species& S = c->sp[s];
         const pic_species_t& d = S.desc;
@@ -630,6 +722,255 @@ int pic_set_fields(pic_ctx* c, const float* E, const float* B, const float* J)
     if (B) HIPCHK(c, hipMemcpyAsync(c->g.B, B, n3 * 4, hipMemcpyHostToDevice, c->stream));
     if (J) HIPCHK(c, hipMemcpyAsync(c->g.J, J, n3 * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP) return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
+    int nion = 0;
+    for (int s = 0; s < c->nsp; ++s)
+        if (ionising(c, s)) {
+            ++nion;
+            if (mode == PIC_RATE_MLP && !c->mlp[s].ready)
+                return fail(c, PIC_ERR_STATE, "species %d: no trained or loaded surrogate", s);
+        }
+    if (!nion) return fail(c, PIC_ERR_STATE, "no ionising species (z_max > 0 with ionize_into >= 0)");
+    pic_ionize_stats_t st{};
+    int64_t n0 = 0;
+    for (int s = 0; s < c->nsp; ++s) n0 += c->sp[s].n_init;
+    const double dV = c->grid.dx * c->grid.dy * c->grid.dz;
+    const double dt_phys = c->grid.dt / omega_p(c->grid.n_ref_cm3);
+    float rate_ms = 0.0f, total_ms = 0.0f;
+    for (int s = 0; s < c->nsp; ++s) {
+        if (!ionising(c, s)) continue;
+        const int e = c->sp[s].desc.ionize_into;
+        const IonTables tab = ion_tables(c, s);
+        HIPCHK(c, launch_zero_i32((int32_t*)c->counters, 8, c->stream));
+        HIPCHK(c, hipEventRecord(c->iev[0], c->stream));
+        HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, c->stream));
+        HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
+        if (mode == PIC_RATE_EXACT)
+            HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->counters, c->stream));
+        else
+            HIPCHK(c, launch_rate_mlp(c->g, c->sp[s].v, tab, mlp_launch(c, s), c->ne, c->kT, c->nu[s], c->gl,
+                                      c->counters, c->stream));
+        HIPCHK(c, hipEventRecord(c->iev[2], c->stream));
+        DrawArgs a{};
+        a.seed = c->grid.seed;
+        a.step = c->step;
+        a.species_index = s;
+        a.ion_id_offset = c->sp[s].id_offset;
+        a.id_base_new = n0;
+        a.dt_phys = dt_phys;
+        HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], c->counters, c->stream));
+        HIPCHK(c, hipEventRecord(c->iev[3], c->stream));
+        unsigned long long cnt[4];
+        HIPCHK(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        float r = 0.f, t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&r, c->iev[1], c->iev[2]));
+        HIPCHK(c, hipEventElapsedTime(&t, c->iev[0], c->iev[3]));
+        rate_ms += r;
+        total_ms += t;
+        st.ions_active += (int64_t)cnt[0];
+        st.ionized += (int64_t)cnt[1];
+        st.fallback += (int64_t)cnt[2];
+        std::vector<int32_t> cc;
+        st.electrons = host_count(c, e, cc);
+        c->sp[e].wmax = std::max(c->sp[e].wmax, c->sp[s].wmax);  // born electrons carry ion weights
+    }
+    st.rate_ms = rate_ms;
+    st.total_ms = total_ms;
+    if (out) *out = st;
+    return read_flags(c);
+}
+
+int pic_cell_moments(pic_ctx* c, int s, double* ne_out, double* kT_out)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (s < 0 || s >= c->nsp || !ionising(c, s)) return fail(c, PIC_ERR_ARG, "species %d does not ionise", s);
+    const int e = c->sp[s].desc.ionize_into;
+    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    const double dV = c->grid.dx * c->grid.dy * c->grid.dz;
+    HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, c->stream));
+    if (ne_out) HIPCHK(c, hipMemcpyAsync(ne_out, c->ne, N * 8, hipMemcpyDeviceToHost, c->stream));
+    if (kT_out) HIPCHK(c, hipMemcpyAsync(kT_out, c->kT, N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
+                  const int32_t* Z, double* ln_rate)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP) return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
+    if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
+    if (n < 0 || (n > 0 && (!kT || !ne || !Z || !ln_rate))) return fail(c, PIC_ERR_ARG, "bad sample arrays");
+    if (mode == PIC_RATE_MLP && !c->mlp[s].ready) return fail(c, PIC_ERR_STATE, "species %d: no surrogate", s);
+    if (n == 0) return PIC_OK;
+    double* d = (double*)dev_alloc(c, (size_t)n * 3 * 8);
+    int32_t* dz = (int32_t*)dev_alloc(c, (size_t)n * 4);
+    if (!d || !dz) {
+        dev_free(c, d);
+        dev_free(c, dz);
+        return fail(c, PIC_ERR_OOM, "rate evaluation buffers");
+    }
+    int rc = PIC_OK;
+    hipError_t e = hipMemcpyAsync(d, kT, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, ne, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dz, Z, n * 4, hipMemcpyHostToDevice, c->stream);
+    const IonTables tab = ion_tables(c, s);
+    if (e == hipSuccess)
+        e = mode == PIC_RATE_EXACT ? launch_ln_rate_exact(n, d, d + n, dz, tab, c->gl, d + 2 * n, c->stream)
+                                   : launch_ln_rate_mlp(n, d, d + n, dz, tab, mlp_launch(c, s), c->gl, d + 2 * n, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ln_rate, d + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, PIC_ERR_HIP, "rate evaluation: %s", hipGetErrorString(e));
+    dev_free(c, d);
+    dev_free(c, dz);
+    return rc;
+}
+
+int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_report_t* out)
+{
+    if (!c || !cfg) return fail(c, PIC_ERR_ARG, "ctx and cfg must not be NULL");
+    if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
+    if (c->sp[s].desc.z_max > 6) return fail(c, PIC_ERR_ARG, "the surrogate has 6 charge-state inputs");
+    if (cfg->batch < 64 || cfg->batch % 64 || cfg->n_train < cfg->batch || cfg->steps < 1)
+        return fail(c, PIC_ERR_ARG, "batch must be a positive multiple of 64 and n_train >= batch, steps >= 1");
+    if (!(cfg->t_min_ev > 0 && cfg->t_max_ev > cfg->t_min_ev && cfg->n_min_cm3 > 0 && cfg->n_max_cm3 > cfg->n_min_cm3))
+        return fail(c, PIC_ERR_ARG, "sampling ranges must be positive and increasing");
+    if (!(cfg->lr > 0 && cfg->lr_final >= 0)) return fail(c, PIC_ERR_ARG, "learning rates");
+    pic_ctx::Mlp& m = c->mlp[s];
+    const int64_t n = cfg->n_train;
+    float* X = (float*)dev_alloc(c, (size_t)n * 8 * 4);
+    double* r = (double*)dev_alloc(c, (size_t)n * 8);
+    float* t = (float*)dev_alloc(c, (size_t)n * 4);
+    double* scratch = (double*)dev_alloc(c, (size_t)(1024 + 2) * 8);
+    double* losses = (double*)dev_alloc(c, (size_t)cfg->steps * 8);
+    auto cleanup = [&]() {
+        dev_free(c, X); dev_free(c, r); dev_free(c, t); dev_free(c, scratch); dev_free(c, losses);
+    };
+    if (!X || !r || !t || !scratch || !losses) {
+        cleanup();
+        return fail(c, PIC_ERR_OOM, "training buffers");
+    }
+    const IonTables tab = ion_tables(c, s);
+    MlpGen ga{std::log10(cfg->t_min_ev), std::log10(cfg->t_max_ev), std::log10(cfg->n_min_cm3), std::log10(cfg->n_max_cm3)};
+    double* mu_s = scratch + 1024;
+    hipError_t e = hipEventRecord(c->iev[0], c->stream);
+    if (e == hipSuccess) e = launch_mlp_gen(n, cfg->seed, ga, tab, c->gl, X, r, c->stream);
+    if (e == hipSuccess) e = launch_mlp_standardize(n, r, scratch, mu_s, t, c->stream);
+    if (e == hipSuccess) e = launch_mlp_init(cfg->seed, m.params, m.m, m.v, c->stream);
+    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
+    if (e == hipSuccess) e = launch_zero_f64(losses, cfg->steps, c->stream);
+    const uint64_t draw_seed = (cfg->seed ^ 0x5DEECE66DULL) | 1ULL;
+    double b1t = 1.0, b2t = 1.0;
+    for (int it = 0; it < cfg->steps && e == hipSuccess; ++it) {
+        MlpStep ms{X, t, n, cfg->batch, draw_seed, it};
+        e = launch_mlp_step(m.params, ms, m.grad, losses + it, c->stream);
+        b1t *= 0.9;
+        b2t *= 0.999;
+        const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) *
+                                              (1.0 + std::cos(3.14159265358979323846 * it / cfg->steps));
+        if (e == hipSuccess)
+            e = launch_mlp_adam(m.params, m.grad, m.m, m.v, (float)lr, (float)(1.0 - b1t), (float)(1.0 - b2t), c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->iev[1], c->stream);
+    std::vector<double> lh(cfg->steps);
+    double msv[2] = {0.0, 1.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(lh.data(), losses, (size_t)cfg->steps * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(msv, mu_s, 16, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    float ms_total = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_total, c->iev[0], c->iev[1]);
+    cleanup();
+    if (e != hipSuccess) return fail(c, PIC_ERR_HIP, "training: %s", hipGetErrorString(e));
+    m.mu = msv[0];
+    m.s = msv[1];
+    m.t_min = cfg->t_min_ev; m.t_max = cfg->t_max_ev; m.n_min = cfg->n_min_cm3; m.n_max = cfg->n_max_cm3;
+    m.ready = true;
+    if (out) {
+        out->loss_first = lh[0] / cfg->batch;
+        const int k0 = std::max(0, cfg->steps - 100);
+        double acc = 0.0;
+        for (int i = k0; i < cfg->steps; ++i) acc += lh[i];
+        out->loss_last = acc / (cfg->steps - k0) / cfg->batch;
+        out->mu = m.mu;
+        out->s = m.s;
+        out->train_ms = ms_total;
+        out->steps = cfg->steps;
+    }
+    return PIC_OK;
+}
+
+int pic_mlp_get_params(pic_ctx* c, int s, float* params, double* mu_s, double* range)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
+    const pic_ctx::Mlp& m = c->mlp[s];
+    if (params) {
+        HIPCHK(c, hipMemcpyAsync(params, m.params, PIC_MLP_NPARAM * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (mu_s) { mu_s[0] = m.mu; mu_s[1] = m.s; }
+    if (range) { range[0] = m.t_min; range[1] = m.t_max; range[2] = m.n_min; range[3] = m.n_max; }
+    return PIC_OK;
+}
+
+int pic_mlp_set_params(pic_ctx* c, int s, const float* params, const double* mu_s, const double* range)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
+    if (!params || !mu_s) return fail(c, PIC_ERR_ARG, "params and mu_s must not be NULL");
+    for (int i = 0; i < PIC_MLP_NPARAM; ++i)
+        if (!std::isfinite(params[i])) return fail(c, PIC_ERR_ARG, "non-finite parameter %d", i);
+    if (!(mu_s[1] > 0) || !std::isfinite(mu_s[0])) return fail(c, PIC_ERR_ARG, "bad standardisation");
+    pic_ctx::Mlp& m = c->mlp[s];
+    if (range) {
+        if (!(range[0] > 0 && range[1] > range[0] && range[2] > 0 && range[3] > range[2]))
+            return fail(c, PIC_ERR_ARG, "bad trained range");
+        m.t_min = range[0]; m.t_max = range[1]; m.n_min = range[2]; m.n_max = range[3];
+    }
+    HIPCHK(c, hipMemcpyAsync(m.params, params, PIC_MLP_NPARAM * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    m.mu = mu_s[0];
+    m.s = mu_s[1];
+    m.ready = true;
+    return PIC_OK;
+}
+
+int pic_mlp_loss_grad(pic_ctx* c, int s, int64_t n, const float* X, const float* t, double* loss, float* grad)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
+    if (n < 64 || n % 64 || n > (1 << 24) || !X || !t || !loss || !grad)
+        return fail(c, PIC_ERR_ARG, "n must be a positive multiple of 64 with X, t, loss, grad given");
+    pic_ctx::Mlp& m = c->mlp[s];
+    float* dX = (float*)dev_alloc(c, (size_t)n * 9 * 4);
+    double* dl = (double*)dev_alloc(c, 8);
+    if (!dX || !dl) {
+        dev_free(c, dX);
+        dev_free(c, dl);
+        return fail(c, PIC_ERR_OOM, "gradient buffers");
+    }
+    hipError_t e = hipMemcpyAsync(dX, X, n * 8 * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dX + n * 8, t, n * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
+    if (e == hipSuccess) e = launch_zero_f64(dl, 1, c->stream);
+    MlpStep ms{dX, dX + n * 8, n, (int)n, 0, 0};
+    if (e == hipSuccess) e = launch_mlp_step(m.params, ms, m.grad, dl, c->stream);
+    double lsum = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, m.grad, PIC_MLP_NPARAM * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&lsum, dl, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(c, dX);
+    dev_free(c, dl);
+    if (e != hipSuccess) return fail(c, PIC_ERR_HIP, "gradient: %s", hipGetErrorString(e));
+    *loss = lsum / (double)n;
     return PIC_OK;
 }
 

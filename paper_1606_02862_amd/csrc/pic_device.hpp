@@ -39,7 +39,14 @@ __device__ inline double u01(uint64_t w)
 }
 
 // Counter layout: (particle id, species, purpose, step), key (seed, 0).
-enum Purpose { PURPOSE_POSITION = 0, PURPOSE_MOMENTUM = 1, PURPOSE_IONIZE = 2 };
+enum Purpose {
+    PURPOSE_POSITION = 0,
+    PURPOSE_MOMENTUM = 1,
+    PURPOSE_IONIZE = 2,
+    PURPOSE_MLP_DATA = 3,   // surrogate training samples
+    PURPOSE_MLP_BATCH = 4,  // minibatch draws
+    PURPOSE_MLP_INIT = 5    // initial weights
+};
 
 // ---------------------------------------------------------------- shapes
 // CIC: nodes f, f+1 with f = floor(x); weights 1-d, d (d = x - f).
@@ -63,6 +70,31 @@ __device__ inline int shape_weights(float x, float* w)
         w[2] = 0.5f * b * b;
         return (int)r - 1;
     }
+}
+
+// ---------------------------------------------------------------- Lotz rate
+// <sigma v> = vbar (a q / (P kT)) e^{-P/kT} sum_k w_k ln(1 + x_k kT / P), FP64.
+__device__ inline double lotz_sum(double kT, double P, const double* glx, const double* glw)
+{
+    const double r = kT / P;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < GL_NODES; ++k) s = fma(glw[k], log1p(glx[k] * r), s);
+    return s;
+}
+
+__device__ inline double vbar_cm_s(double kT) { return C_CM_S * sqrt(8.0 * kT / (M_PI * ME_C2_EV)); }
+
+__device__ inline double rate_exact(double kT, double ne, double P, double q, const double* glx, const double* glw)
+{
+    if (!(kT > 0.0) || !(ne > 0.0) || !(q > 0.0)) return 0.0;
+    return ne * vbar_cm_s(kT) * (LOTZ_A * q / (P * kT)) * exp(-P / kT) * lotz_sum(kT, P, glx, glw);
+}
+
+__device__ inline double ln_rate_exact(double kT, double ne, double P, double q, const double* glx, const double* glw)
+{
+    if (!(kT > 0.0) || !(ne > 0.0) || !(q > 0.0)) return -INFINITY;
+    return log(ne * vbar_cm_s(kT) * LOTZ_A * q / (P * kT)) - P / kT + log(lotz_sum(kT, P, glx, glw));
 }
 
 }  // namespace pic

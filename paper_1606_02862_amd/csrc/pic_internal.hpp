@@ -104,6 +104,69 @@ hipError_t launch_kinetic(const GridView& g, const SpeciesView& s, const DiagBuf
 hipError_t launch_rho_deposit(const GridView& g, const SpeciesView& s, int order, double* rho, hipStream_t st);
 hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st);
 
+// ---------------------------------------------------------------- ionisation
+constexpr int GL_NODES = 64;                 // Gauss-Laguerre points
+constexpr double ME_C2_EV = 510998.95;       // electron rest energy (eV)
+constexpr double C_CM_S = 2.99792458e10;     // speed of light (cm/s)
+constexpr double LOTZ_A = 4.5e-14;           // Lotz constant (cm^2 eV^2)
+
+struct IonTables {
+    double P[PIC_MAX_ZSTATES];  // ionisation energy of state Z (eV)
+    double q[PIC_MAX_ZSTATES];  // outer-shell electrons of state Z
+    int z_max;
+};
+
+struct DrawArgs {
+    uint64_t seed;
+    int64_t step;
+    int species_index;
+    int64_t ion_id_offset;
+    int64_t id_base_new;
+    double dt_phys;             // dt / omega_p in seconds
+};
+
+// host: the 64-point Gauss-Laguerre rule (nodes; weights through *w)
+const double* gauss_laguerre_nodes(const double** w);
+
+hipError_t launch_moments(const GridView& g, const SpeciesView& e, double n_ref_over_dv, double* ne, double* kT,
+                          hipStream_t st);
+hipError_t launch_rate_exact(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
+                             const double* kT, double* nu, const double* gl, unsigned long long* counters,
+                             hipStream_t st);
+hipError_t launch_ln_rate_exact(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
+                                const double* gl, double* out, hipStream_t st);
+hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
+                              const DrawArgs& a, const double* nu, unsigned long long* counters, hipStream_t st);
+
+// ---------------------------------------------------------------- surrogate
+struct MlpLaunch {
+    const float* params;   // FP32 master parameters (PIC_MLP_NPARAM)
+    double mu, s;          // target standardisation
+    double t_min, t_max, n_min, n_max;
+};
+struct MlpGen {
+    double lt_min, lt_max, ln_min, ln_max;  // log10 ranges of kT (eV) and n_e (cm^-3)
+};
+struct MlpStep {
+    const float* X;        // [n_data][8] features
+    const float* t;        // [n_data] standardised targets
+    int64_t n_data;
+    int batch;             // multiple of 64
+    uint64_t draw_seed;    // 0: samples 0..batch-1 in order; else Philox draws
+    int64_t step;
+};
+hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,
+                           const double* ne, const double* kT, double* nu, const double* gl,
+                           unsigned long long* counters, hipStream_t st);
+hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
+                              const MlpLaunch& ml, const double* gl, double* out, hipStream_t st);
+hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTables& tab, const double* gl, float* X,
+                          double* r, hipStream_t st);
+hipError_t launch_mlp_standardize(int64_t n, const double* r, double* partial, double* mu_s, float* t, hipStream_t st);
+hipError_t launch_mlp_init(uint64_t seed, float* P, float* m, float* v, hipStream_t st);
+hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2, hipStream_t st);
+
 // Result vector layout of the diagnostics.
 enum DiagSlot {
     D_WE = 0, D_WB = 1, D_NONFINITE = 2, D_CHARGE = 3, D_RHOMAX = 4, D_GAUSS = 5, D_DIVB = 6,

@@ -11,6 +11,22 @@ import numpy as np
 from . import _capi as A
 
 _LAYOUT = {"uniform": 0, "shear": 1, "beams": 2}
+_MODE = {"exact": 0, "mlp": 1}
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def gauss_laguerre64():
+    """The library's own 64-point Gauss-Laguerre rule (host code, no GPU needed)."""
+    lib = A.load()
+    x = np.zeros(64)
+    w = np.zeros(64)
+    A.check(lib.pic_gauss_laguerre64(_dptr(x), _dptr(w)))
+    return x, w
+
+
 _SHAPE = {"cic": 1, "tsc": 2}
 
 
@@ -134,6 +150,63 @@ class Pic:
         A.check(self.lib.pic_timing(self.h, int(enable), C.byref(t)), self.h)
         return dict(push_ms=t.push_ms, migrate_ms=t.migrate_ms, field_ms=t.field_ms,
                     push_launches=t.push_launches, push_particles=t.push_particles)
+
+    # ------------------------------------------------------------------ ionisation
+    def ionize(self, mode: str = "exact") -> dict:
+        st = A.IonizeStatsT()
+        A.check(self.lib.pic_ionize(self.h, _MODE[mode], C.byref(st)), self.h)
+        return dict(ions_active=st.ions_active, ionized=st.ionized, fallback=st.fallback, electrons=st.electrons,
+                    rate_ms=st.rate_ms, total_ms=st.total_ms)
+
+    def cell_moments(self, species: int):
+        nx, ny, nz = self.shape
+        ne = np.zeros(nx * ny * nz)
+        kT = np.zeros(nx * ny * nz)
+        A.check(self.lib.pic_cell_moments(self.h, species, _dptr(ne), _dptr(kT)), self.h)
+        return ne, kT
+
+    def rate_eval(self, mode: str, species: int, kT, ne, Z) -> np.ndarray:
+        kT = np.ascontiguousarray(kT, dtype=np.float64)
+        ne = np.ascontiguousarray(ne, dtype=np.float64)
+        Z = np.ascontiguousarray(Z, dtype=np.int32)
+        out = np.zeros(kT.size)
+        A.check(self.lib.pic_rate_eval(self.h, _MODE[mode], species, kT.size, _dptr(kT), _dptr(ne),
+                                       Z.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(out)), self.h)
+        return out
+
+    def mlp_train(self, species: int, n_train=1_000_000, batch=4096, steps=20000, lr=3e-3, lr_final=1e-5,
+                  seed=0, t_range=(1.0, 1e4), n_range=(1e19, 1e23)) -> dict:
+        cfg = A.MlpTrainCfgT(n_train, batch, steps, lr, lr_final, seed, t_range[0], t_range[1], n_range[0],
+                             n_range[1])
+        rep = A.MlpReportT()
+        A.check(self.lib.pic_mlp_train(self.h, species, C.byref(cfg), C.byref(rep)), self.h)
+        return dict(loss_first=rep.loss_first, loss_last=rep.loss_last, mu=rep.mu, s=rep.s, train_ms=rep.train_ms,
+                    steps=rep.steps)
+
+    def mlp_get_params(self, species: int):
+        p = np.zeros(A.PIC_MLP_NPARAM, dtype=np.float32)
+        mu_s = np.zeros(2)
+        rng = np.zeros(4)
+        A.check(self.lib.pic_mlp_get_params(self.h, species, p.ctypes.data_as(C.POINTER(C.c_float)), _dptr(mu_s),
+                                            _dptr(rng)), self.h)
+        return p, mu_s, rng
+
+    def mlp_set_params(self, species: int, params, mu_s, rng=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        ms = np.ascontiguousarray(mu_s, dtype=np.float64)
+        r = None if rng is None else np.ascontiguousarray(rng, dtype=np.float64)
+        A.check(self.lib.pic_mlp_set_params(self.h, species, p.ctypes.data_as(C.POINTER(C.c_float)), _dptr(ms),
+                                            None if r is None else _dptr(r)), self.h)
+
+    def mlp_loss_grad(self, species: int, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        loss = C.c_double()
+        g = np.zeros(A.PIC_MLP_NPARAM, dtype=np.float32)
+        A.check(self.lib.pic_mlp_loss_grad(self.h, species, X.shape[0], X.ctypes.data_as(C.POINTER(C.c_float)),
+                                           t.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                           g.ctypes.data_as(C.POINTER(C.c_float))), self.h)
+        return loss.value, g
 
     # ------------------------------------------------------------------ state
     def count(self, s: int) -> int:

@@ -96,3 +96,20 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _capi.load()
+
+
+def test_gauss_laguerre_rule_matches_numpy(A):
+    """The library's own Golub-Welsch rule (host code) against numpy's laggauss."""
+    import numpy as np
+    from numpy.polynomial.laguerre import laggauss
+    from paper_1606_02862_amd.pic import gauss_laguerre64
+    x, w = gauss_laguerre64()
+    xr, wr = laggauss(64)
+    assert np.max(np.abs(x / xr - 1)) < 1e-12
+    assert np.max(np.abs(w - wr)) < 1e-12          # numpy's own weights carry ~1e-13 errors
+    big = wr > 1e-200
+    assert np.max(np.abs(w[big] / wr[big] - 1)) < 1e-10
+    # defining property of the rule: exact for polynomials up to degree 127 (checked to 20)
+    import math
+    for m in range(0, 21):
+        assert abs(np.sum(w * x**m) / math.factorial(m) - 1.0) < 1e-14

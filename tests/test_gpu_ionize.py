@@ -1,0 +1,253 @@
+"""GPU parity of the Monte Carlo ionisation step and of the learned rate
+surrogate against the FP64 oracle, through the C ABI.
+
+Exact path: ln nu from the GPU's FP64 64-point Gauss-Laguerre quadrature
+agrees with the oracle's to 1e-12; cell moments agree to 1e-12; ionisation
+decisions on the same Philox uniforms agree except where |r - p| is below the
+FP64 rounding of p, and every new electron matches its ion.
+Surrogate: BF16-MFMA training gradients within 2e-2 (relative, per tensor) of
+the oracle's FP64 backpropagation with cosine > 0.999; after training on GPU
+the median relative rate error on a held-out set is <= 1 %, and the network
+beats its analytic prior alone.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import ionize, mlp
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_02862_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _carbon_cfg(box=(16, 16, 8)):
+    return workloads.reduced(3, *box)
+
+
+# ---------------------------------------------------------------------------
+# exact rates and moments
+
+def test_exact_rate_matches_oracle(P):
+    cfg = _carbon_cfg()
+    T, ne, Z = workloads.loguniform_rate_inputs(11, 20000, t_range=(0.5, 3e4), n_range=(1e18, 1e24))
+    with P.Pic(cfg) as pic:
+        got = pic.rate_eval("exact", 1, T, ne, Z)
+    Pz = np.array(workloads.CARBON_IONIZATION_EV)[Z]
+    qz = np.array(workloads.CARBON_LOTZ_Q)[Z]
+    want = ionize.ln_rate_exact(T, ne, Pz, qz)
+    fin = np.isfinite(want)
+    err = np.abs(got[fin] - want[fin])
+    _print("exact ln-rate max abs err", err.max())
+    assert np.all(np.isfinite(got[fin]))
+    assert err.max() < 1e-12 * np.maximum(1.0, np.abs(want[fin])).max()
+
+
+def test_cell_moments_match_oracle(P):
+    cfg = _carbon_cfg()
+    with P.Pic(cfg) as pic:
+        pic.step(3)
+        st = parity.pull_state(pic, oracle.init_state(cfg))
+        ne, kT = pic.cell_moments(1)
+    g = st.grid
+    ne_ref, kT_ref = ionize.density_temperature(ionize.cell_moments(st, 0), g.dx * g.dy * g.dz,
+                                                cfg["grid"]["n_ref_cm3"])
+    assert np.max(np.abs(ne / ne_ref - 1)) < 1e-12
+    assert np.max(np.abs(kT - kT_ref) / kT_ref) < 1e-10
+
+
+def _shared_carbon_state(pic, cfg, warm=4):
+    st = oracle.init_state(cfg)
+    oracle.step(st, warm)
+    s0 = parity.shared_start(pic, st)
+    s0.step = 0  # the handle has taken no cycles: its ionisation draws use step 0
+    return s0
+
+
+def test_ionize_exact_matches_oracle(P):
+    cfg = _carbon_cfg()
+    ncell = 16 * 16 * 8
+    n_e0, n_c0 = ncell * 8, ncell * 4
+    with P.Pic(cfg) as pic:
+        s0 = _shared_carbon_state(pic, cfg)
+        ref = s0.copy()
+        d = ionize.ionize_step(ref, cfg, 0, 1, n_e0 + n_c0, n_e0, return_details=True)
+        stats = pic.ionize("exact")
+        got = parity.pull_state(pic, s0)
+    fire_ref = d["fire"]
+    _print("ionised gpu/ref", stats["ionized"], int(fire_ref.sum()), "active", stats["ions_active"])
+    assert stats["ions_active"] == n_c0
+    assert fire_ref.sum() > 20  # the test state must actually ionise
+    # decisions may differ only where r is within FP64 rounding of p
+    zg = got.species[1].zstate
+    zr = ref.species[1].zstate
+    differ = np.nonzero(zg != zr)[0]
+    assert len(differ) <= 2
+    for k in differ:
+        assert abs(d["uniforms"][k] - d["prob"][k]) < 1e-12 * max(d["prob"][k], 1e-300)
+    if len(differ) == 0:
+        assert stats["ionized"] == int(fire_ref.sum())
+        # new electrons: same ids, born on their ion with its momentum and weight
+        eg, er = got.species[0], ref.species[0]
+        er.sort_by_id()
+        assert np.array_equal(eg.id, er.id)
+        for a in ("x", "y", "z", "ux", "uy", "uz", "w"):
+            assert np.array_equal(getattr(eg, a), getattr(er, a)), a
+
+
+def test_ionisation_conserves_charge_over_a_run(P):
+    """Gauss's law G = div E - rho keeps its reference value through PIC
+    cycles interleaved with ionisation (each event adds +1 to an ion and a -1
+    electron at the same position)."""
+    cfg = _carbon_cfg()
+    with P.Pic(cfg) as pic:
+        total = 0
+        for _ in range(5):
+            pic.step(2)
+            total += pic.ionize("exact")["ionized"]
+        m = pic.moments()
+    _print("ionised over run", total, "gauss", m["gauss_max"], "rho_max", m["rho_max"])
+    assert total > 0
+    assert m["gauss_max"] <= 1e-4 * m["rho_max"]
+
+
+def test_ionize_requires_surrogate_before_mlp_mode(P):
+    cfg = _carbon_cfg((8, 8, 4))
+    with P.Pic(cfg) as pic:
+        with pytest.raises(P.PicError) as e:
+            pic.ionize("mlp")
+        assert e.value.code == -7
+
+
+# ---------------------------------------------------------------------------
+# surrogate: gradients, training, accuracy, gain
+
+def _bf16(a):
+    a = np.asarray(a, dtype=np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def _flat(p):
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"]])
+
+
+def _unflat(v):
+    o, d = 0, {}
+    for k, shape in (("W1", (64, 8)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        d[k] = np.asarray(v[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return d
+
+
+def test_mlp_gradient_matches_oracle_backprop(P):
+    cfg = _carbon_cfg((8, 8, 4))
+    p = mlp.init_params(4)
+    flat = _bf16(_flat(p))           # BF16-representable weights on both sides
+    pref = _unflat(flat)
+    T, ne, Z = workloads.loguniform_rate_inputs(12, 4096)
+    X = mlp.features(T, ne, Z)
+    X = _bf16(X).astype(np.float64)  # features the GPU sees exactly
+    t = workloads.rng(13).normal(size=4096)
+    loss_ref, g_ref = mlp.loss_and_grad(pref, X, t)
+    with P.Pic(cfg) as pic:
+        pic.mlp_set_params(1, flat, [0.0, 1.0])
+        loss, g = pic.mlp_loss_grad(1, X, t)
+    gg = _unflat(g)
+    _print("loss gpu/ref", loss, loss_ref)
+    assert abs(loss / loss_ref - 1) < 2e-2
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a, b = gg[k].ravel(), g_ref[k].ravel()
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        _print(k, "rel", rel, "cos", cos)
+        assert rel < 2e-2 and cos > 0.999, k
+
+
+@pytest.fixture(scope="module")
+def trained(P):
+    """Train the surrogate on the GPU with the full recipe (1M samples)."""
+    cfg = _carbon_cfg((8, 8, 4))
+    tr = dict(workloads.MLP_TRAIN)
+    pic = P.Pic(cfg)
+    rep = pic.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **tr)
+    _print("training report", rep)
+    yield pic, rep
+    pic.close()
+
+
+def test_mlp_training_converges(trained):
+    pic, rep = trained
+    assert rep["loss_last"] < 1e-2 * rep["loss_first"]
+    assert rep["steps"] == workloads.MLP_TRAIN["steps"]
+
+
+def test_mlp_rate_error_and_gain_on_heldout_set(trained):
+    """Median relative rate error <= 1 % against the exact GL-64 rate (the
+    judge), on held-out log-uniform inputs; the analytic prior alone is
+    reported for the gain."""
+    pic, _ = trained
+    T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)
+    got = pic.rate_eval("mlp", 1, T, ne, Z)
+    Pz = np.array(workloads.CARBON_IONIZATION_EV)[Z]
+    qz = np.array(workloads.CARBON_LOTZ_Q)[Z]
+    exact = ionize.ln_rate_exact(T, ne, Pz, qz)
+    prior = mlp.ln_rate_prior(T, ne, Pz, qz)
+    rel = np.abs(np.expm1(got - exact))
+    relp = np.abs(np.expm1(prior - exact))
+    _print("surrogate median/p99/max", np.median(rel), np.quantile(rel, 0.99), rel.max(),
+           "prior median", np.median(relp))
+    assert np.median(rel) <= 1e-2
+    assert np.median(rel) < 0.1 * np.median(relp)
+
+
+def test_mlp_out_of_range_uses_exact_fallback(trained):
+    pic, _ = trained
+    T = np.array([0.3, 5e4, 100.0, 100.0])
+    ne = np.array([1e21, 1e21, 1e17, 1e25])
+    Z = np.array([0, 1, 2, 3])
+    got = pic.rate_eval("mlp", 1, T, ne, Z)
+    want = pic.rate_eval("exact", 1, T, ne, Z)
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_mlp_params_roundtrip(trained):
+    pic, _ = trained
+    p, ms, rng = pic.mlp_get_params(1)
+    assert np.all(np.isfinite(p)) and ms[1] > 0
+    assert tuple(rng) == (1.0, 1e4, 1e19, 1e23)
+
+
+def test_ionize_mlp_tracks_exact(trained, P):
+    """On one state, the surrogate's per-ion rates match the exact ones to the
+    surrogate's accuracy, and the ionisation count to binomial noise."""
+    pic_tr, _ = trained
+    params, ms, rng = pic_tr.mlp_get_params(1)
+    cfg = _carbon_cfg()
+    counts = {}
+    for mode in ("exact", "mlp"):
+        with P.Pic(cfg) as pic:
+            pic.mlp_set_params(1, params, ms, rng)
+            pic.step(2)
+            counts[mode] = pic.ionize(mode)
+    _print(counts)
+    a, b = counts["exact"]["ionized"], counts["mlp"]["ionized"]
+    assert abs(a - b) <= 5 * np.sqrt(max(a, 1)) + 2
+    assert counts["mlp"]["ions_active"] == counts["exact"]["ions_active"]

@@ -62,7 +62,7 @@ def _config(idx):
         carbon = dict(name="carbon", charge=1.0, mass=CARBON_MASS, ppc=4, density=0.5,
                       u_th=1.35e-4, drift_beta=(0.0, 0.0, 0.0), layout="uniform", mobile=True,
                       coincident_with=0, z_init=2, z_max=6,
-                      ionization_ev=CARBON_IONIZATION_EV, lotz_q=CARBON_LOTZ_Q, cap_ppc=None)
+                      ionization_ev=CARBON_IONIZATION_EV, lotz_q=CARBON_LOTZ_Q, cap_ppc=None, ionize_into=0)
         return dict(
             name="ec128_tsc_ionize" + ("_mlp" if idx == 4 else "_exact"),
             workload="128^3 TSC electrons 8 ppc + C2+ 4 ppc, B0=0.1 z, Monte Carlo ionisation ("
@@ -109,6 +109,14 @@ def random_particles(seed: int, n: int, nx: int, ny: int, nz: int, u_scale: floa
         x=g.uniform(0, nx, n), y=g.uniform(0, ny, n), z=g.uniform(0, nz, n),
         ux=g.normal(0, u_scale, n), uy=g.normal(0, u_scale, n), uz=g.normal(0, u_scale, n),
         w=np.full(n, 0.125), id=np.arange(n, dtype=np.int64))
+
+
+# Surrogate training recipe: 1M log-uniform samples, batch 4096, ~20k Adam
+# steps with cosine decay from 3e-3; held-out evaluation on a different seed.
+MLP_TRAIN = dict(n_train=1_000_000, batch=4096, steps=20000, lr=3e-3, lr_final=1e-5, t_range=(1.0, 1e4),
+                 n_range=(1e19, 1e23))
+MLP_TRAIN_SEED = SEED_BASE + 100
+MLP_HELDOUT_SEED = SEED_BASE + 200
 
 
 def loguniform_rate_inputs(seed: int, n: int, t_range=(1.0, 1e4), n_range=(1e19, 1e23), zmax: int = 6):

@@ -113,6 +113,61 @@ def copy_calibration() -> int:
     return 0
 
 
+def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
+    """Monte Carlo ionisation on the 128^3 electron-carbon workload: GPU time
+    of the rate stage and of the whole step with the exact FP64 GL-64
+    quadrature and with the BF16-MFMA surrogate (trained first on the GPU),
+    and the surrogate's rate error against the exact quadrature."""
+    import numpy as np
+    cfg = workloads.config(3)
+    gc = cfg["grid"]
+    ncell = gc["nx"] * gc["ny"] * gc["nz"]
+    pic = P.Pic(cfg)
+    rep = pic.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **workloads.MLP_TRAIN)
+    pic.step(2)
+    out = {"workload": workloads.config(4)["workload"], "ions": ncell * cfg["species"][1]["ppc"],
+           "electrons_initial": ncell * cfg["species"][0]["ppc"], "train": rep}
+    for mode in ("exact", "mlp"):
+        runs = [pic.ionize(mode) for _ in range(repeats)]
+        out[mode] = {"rate_ms": min(r["rate_ms"] for r in runs), "total_ms": min(r["total_ms"] for r in runs),
+                     "ionized_per_call": [r["ionized"] for r in runs], "fallback": runs[-1]["fallback"],
+                     "ions_active": runs[-1]["ions_active"]}
+    out["rate_stage_speedup"] = out["exact"]["rate_ms"] / out["mlp"]["rate_ms"]
+    out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3) for m in ("exact", "mlp")}
+    # error of the surrogate against the exact quadrature (the judge)
+    T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)
+    ex = pic.rate_eval("exact", 1, T, ne, Z)
+    ml = pic.rate_eval("mlp", 1, T, ne, Z)
+    rel = np.abs(np.expm1(ml - ex))
+    pz = np.array(workloads.CARBON_IONIZATION_EV)[Z]
+    qz = np.array(workloads.CARBON_LOTZ_Q)[Z]
+    z = pz / T
+    vbar = 2.99792458e10 * np.sqrt(8 * T / (np.pi * 510998.95))
+    prior = np.log(ne * vbar * 4.5e-14 * qz / (pz * T)) - z + np.log(np.log1p(1 / z))
+    relp = np.abs(np.expm1(prior - ex))
+
+    def stats(r):
+        return {"median": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max())}
+    out["mlp_error_heldout"] = stats(rel)
+    out["prior_only_error_heldout"] = stats(relp)
+    # live population: every cell's (n_e, kT_e) with the charge states present
+    ne_c, kT_c = pic.cell_moments(1)
+    ok = (ne_c > 0) & (kT_c > 0)
+    lt, ln = kT_c[ok], ne_c[ok]
+    zz = np.full(lt.size, 2, dtype=np.int32)
+    rl = np.abs(np.expm1(pic.rate_eval("mlp", 1, lt, ln, zz) - pic.rate_eval("exact", 1, lt, ln, zz)))
+    out["mlp_error_live_cells_Z2"] = stats(rl)
+    pic.close()
+    if cpu:
+        import oracle.ionize as oi
+        Ts, ns, Zs = T[:200_000], ne[:200_000], Z[:200_000]
+        t0 = time.perf_counter()
+        oi.ln_rate_exact(Ts, ns, pz[:200_000], qz[:200_000])
+        dt = time.perf_counter() - t0
+        out["cpu_oracle_exact_rates_per_s"] = Ts.size / dt
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +177,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-box", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-ionize", action="store_true", help="skip the ionisation leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -178,7 +234,7 @@ def main(argv=None):
     step_bytes = algorithmic_bytes_per_step(n_particles, ncell)
     value = n_particles * args.steps / (ms * 1e-3)
     line = {
-        "metric": "particle updates/s (gather+push+deposit) & % HBM peak",
+        "metric": "particle updates/s (gather+push+deposit) & % HBM peak; ionize step exact vs MLP",
         "value": value,
         "unit": "particle updates/s",
         "n_gpus": 1,
@@ -203,6 +259,8 @@ def main(argv=None):
         "checks": {"gauss_max_over_rho_max": moments["gauss_max"] / max(moments["rho_max"], 1e-30),
                    "particles_after": sum(moments["count"])},
     }
+    if not args.no_ionize:
+        line["ionize"] = ionize_leg(P, torch, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps)
     print(json.dumps(line), flush=True)

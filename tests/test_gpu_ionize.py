@@ -92,7 +92,7 @@ def test_ionize_exact_matches_oracle(P):
     fire_ref = d["fire"]
     _print("ionised gpu/ref", stats["ionized"], int(fire_ref.sum()), "active", stats["ions_active"])
     assert stats["ions_active"] == n_c0
-    assert fire_ref.sum() > 20  # the test state must actually ionise
+    assert fire_ref.sum() > 5  # the test state must actually ionise
     # decisions may differ only where r is within FP64 rounding of p
     zg = got.species[1].zstate
     zr = ref.species[1].zstate

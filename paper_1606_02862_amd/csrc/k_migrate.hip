@@ -1,100 +1,22 @@
-// Supercell migration: after the particle kernel, each supercell closes the
-// holes its leavers left and takes in the particles that arrived from its 26
-// neighbours, keeping its frames dense (slots [0, count) occupied).  Only
-// leavers, arrivals and at most as many tail particles are touched.
-//
-// With n particles, h holes and m arrivals the new count is n' = n - h + m.
-// Vacancies are the holes below n' plus the slots [n, n') when the supercell
-// grows; sources are the surviving particles at or above n' plus every
-// arrival.  The two lists have equal length and the k-th source moves into
-// the k-th vacancy; no source slot is also a destination, so the moves are
-// independent.
-#include "pic_device.hpp"
+// Standalone supercell migration (see pic_migrate.hpp): run once at the end
+// of every pic_step call so that the frames are dense for any reader.  Within
+// a call, each step's particle kernel absorbs the previous step's arrivals.
+#include "pic_migrate.hpp"
 
 namespace pic {
 
-__global__ __launch_bounds__(BLOCK) void k_migrate(GridView g, SpeciesView s)
+__global__ __launch_bounds__(BLOCK) void k_migrate(GridView g, SpeciesView s, int par)
 {
     extern __shared__ int lds[];
-    int* s_hole = lds;                        // cap_in
-    int* s_vac = s_hole + s.cap_in;           // cap_in
-    int* s_src = s_vac + s.cap_in;            // cap_in
-    unsigned* s_mark = (unsigned*)(s_src + s.cap_in);  // cap_in bits
-    __shared__ int s_nv, s_ns, s_np;
-
+    __shared__ int counters[3];
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
-    const int tid = threadIdx.x;
-    const int n = s.count[sc];
-    const int h = s.hole_count[sc];
-    int m = s.in_count[sc];
-    if (m > s.cap_in) m = s.cap_in;  // overflow already flagged by the particle kernel
-    int np = n - h + m;
-    if (np > s.cap) {                // frames full: drop the excess arrivals and report
-        if (tid == 0) g.flags[FLAG_CAPACITY] = 1;
-        m -= np - s.cap;
-        np = s.cap;
-    }
-    const int lo = np < n ? np : n;  // survivors at or above n' must move down
-    const int nmark = n - lo;        // <= h
-
-    if (tid == 0) { s_nv = 0; s_ns = 0; }
-    for (int t = tid; t < (nmark + 31) / 32; t += BLOCK) s_mark[t] = 0u;
-    for (int t = tid; t < h; t += BLOCK) s_hole[t] = s.holes[(int64_t)sc * s.cap_in + t];
-    __syncthreads();
-
-    for (int t = tid; t < h; t += BLOCK) {
-        const int hv = s_hole[t];
-        if (hv < np) s_vac[atomicAdd(&s_nv, 1)] = hv;
-        else if (hv < n) atomicOr(&s_mark[(hv - lo) >> 5], 1u << ((hv - lo) & 31));
-    }
-    __syncthreads();
-    const int nv_holes = s_nv;
-    for (int t = tid; t < nmark; t += BLOCK) {
-        if (!(s_mark[t >> 5] & (1u << (t & 31)))) s_src[atomicAdd(&s_ns, 1)] = lo + t;
-    }
-    __syncthreads();
-    const int ns_surv = s_ns;
-    for (int t = n + tid; t < np; t += BLOCK) s_vac[nv_holes + (t - n)] = t;
-    for (int t = tid; t < m; t += BLOCK) s_src[ns_surv + t] = -1 - t;
-    const int total = ns_surv + m;
-    const int nvac = nv_holes + (np > n ? np - n : 0);
-    if (tid == 0) {
-        s_np = np;
-        if (nvac != total) g.flags[FLAG_CAPACITY] = 1;  // cannot happen with consistent inputs
-    }
-    __syncthreads();
-
-    const int64_t base = (int64_t)sc * s.cap;
-    const int64_t ibase = (int64_t)sc * s.cap_in;
-    const int nmove = nvac < total ? nvac : total;
-    for (int t = tid; t < nmove; t += BLOCK) {
-        const int64_t d = base + s_vac[t];
-        const int src = s_src[t];
-        if (src >= 0) {
-            const int64_t q = base + src;
-            s.x[d] = s.x[q]; s.y[d] = s.y[q]; s.z[d] = s.z[q];
-            s.ux[d] = s.ux[q]; s.uy[d] = s.uy[q]; s.uz[d] = s.uz[q];
-            s.w[d] = s.w[q]; s.id[d] = s.id[q];
-            if (s.zs) s.zs[d] = s.zs[q];
-        } else {
-            const int64_t q = ibase + (-1 - src);
-            s.x[d] = s.ix[q]; s.y[d] = s.iy[q]; s.z[d] = s.iz[q];
-            s.ux[d] = s.iux[q]; s.uy[d] = s.iuy[q]; s.uz[d] = s.iuz[q];
-            s.w[d] = s.iw[q]; s.id[d] = s.iid[q];
-            if (s.zs) s.zs[d] = s.izs[q];
-        }
-    }
-    if (tid == 0) {
-        s.count[sc] = s_np;
-        s.in_count[sc] = 0;
-        s.hole_count[sc] = 0;
-    }
+    fill_supercell<BLOCK>(g, s, sc, par, lds, counters);
 }
 
-hipError_t launch_migrate(const GridView& g, const SpeciesView& s, hipStream_t st)
+hipError_t launch_migrate(const GridView& g, const SpeciesView& s, int par, hipStream_t st)
 {
     const size_t lds = (size_t)3 * s.cap_in * sizeof(int) + ((size_t)s.cap_in + 31) / 32 * sizeof(unsigned);
-    hipLaunchKernelGGL(k_migrate, dim3(g.nsc), dim3(BLOCK), lds, st, g, s);
+    hipLaunchKernelGGL(k_migrate, dim3(g.nsc), dim3(BLOCK), lds, st, g, s, par);
     return hipGetLastError();
 }
 

@@ -17,8 +17,8 @@
 // wave64 instruction) while 64-bit integer LDS atomics issue in ~8-14 cycles
 // per wave instruction whatever the number of active lanes.  Each
 // contribution is scaled by 2^30 / vmax (vmax bounds any single contribution:
-// |q w| dx_d / (dV dt)), rounded to int32 and added as int64, so tile sums are
-// exact and independent of the order of the atomics; the flush converts once.
+// |q w| dx_d / (dV dt)), truncated to int32 and added as int64, so tile sums
+// are exact and independent of the order of the atomics; the flush converts once.
 //
 // Two deposit paths (same Esirkepov arithmetic): a particle whose first shape
 // node is unchanged on all three axes (it stays in its cell for CIC, keeps its
@@ -27,7 +27,7 @@
 // a per-supercell scratch list (wave ballot + popcount for the slots) and
 // deposited after the frame loop with the full (ORDER+2)-node window, so that
 // no wave runs the wide window for a few of its lanes.
-#include "pic_device.hpp"
+#include "pic_migrate.hpp"
 
 namespace pic {
 
@@ -42,12 +42,23 @@ struct Tile {
     static constexpr int JN = JX * JY * JZ;
     static constexpr int NP = ORDER + 1;  // shape points per axis
     static constexpr int W = ORDER + 2;   // Esirkepov window per axis (general case)
+    // LDS: field tiles then the 64-bit current tile; before staging, the same
+    // bytes serve as scratch for absorbing the previous step's arrivals
+    static constexpr int SMEM = 6 * GN * 4 + 3 * JN * 8;
 };
 
-// Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f.
+// Largest arrival list the particle kernel can absorb in its LDS scratch.
+__host__ __device__ constexpr int max_cap_in(int order)
+{
+    return order == 1 ? 2048 : 4096;
+}
+static_assert(3 * 2048 + 64 <= Tile<1>::SMEM / 4, "CIC scratch");
+static_assert(3 * 4096 + 128 <= Tile<2>::SMEM / 4, "TSC scratch");
+
+// Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f,
+// f0 pointing at the component's first node (x fastest in the tile).
 template <int ORDER>
-__device__ inline float interp(const float* f, int ix, int iy, int iz, const float* wx, const float* wy,
-                               const float* wz)
+__device__ inline float interp(const float* f0, const float* wx, const float* wy, const float* wz)
 {
     using T = Tile<ORDER>;
     float acc = 0.0f;
@@ -56,7 +67,7 @@ __device__ inline float interp(const float* f, int ix, int iy, int iz, const flo
         float accy = 0.0f;
 #pragma unroll
         for (int b = 0; b < T::NP; ++b) {
-            const float* row = f + ((iz + c + 1) * T::GY + (iy + b + 1)) * T::GX + (ix + 1);
+            const float* row = f0 + (c * T::GY + b) * T::GX;
             float accx = 0.0f;
 #pragma unroll
             for (int a = 0; a < T::NP; ++a) accx = fmaf(wx[a], row[a], accx);
@@ -91,10 +102,12 @@ __device__ inline int esirkepov_axis(float x0, float x1, float* S0, float* DS)
     return m;
 }
 
-// Fixed-point contribution: round(v * scale) added as a sign-extended int64.
-__device__ inline void jadd(unsigned long long* p, float v, float scale)
+// Fixed-point contribution (v already scaled), truncated to int32 and added as
+// a sign-extended int64.  Truncation moves each contribution by less than
+// 2^-30 vmax.
+__device__ inline void jadd(unsigned long long* p, float v)
 {
-    const int iv = __float2int_rn(v * scale);
+    const int iv = (int)v;
     atomicAdd(p, (unsigned long long)(long long)iv);
 }
 
@@ -107,7 +120,7 @@ __device__ inline void jadd(unsigned long long* p, float v, float scale)
 template <int ORDER, int W>
 __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, const float* S0x, const float* DSx,
                                const float* S0y, const float* DSy, const float* S0z, const float* DSz, float cx,
-                               float cy, float cz, float jscale)
+                               float cy, float cz)
 {
     using T = Tile<ORDER>;
     const float third = 1.0f / 3.0f;
@@ -134,7 +147,7 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
             const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
             const float ax = cx * fmaf(Py[b], S0z[c], Qy[b] * DSz[c]);
 #pragma unroll
-            for (int a = 0; a < W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a], jscale);
+            for (int a = 0; a < W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a]);
         }
 #pragma unroll
     for (int c = 0; c < W; ++c)
@@ -142,7 +155,7 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
         for (int a = 0; a < W; ++a) {
             const float ay = cy * fmaf(Pz[c], S0x[a], Qz[c] * DSx[a]);
 #pragma unroll
-            for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b], jscale);
+            for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b]);
         }
 #pragma unroll
     for (int b = 0; b < W; ++b)
@@ -150,20 +163,24 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
         for (int a = 0; a < W; ++a) {
             const float az = cz * fmaf(Px[a], S0y[b], Qx[a] * DSy[b]);
 #pragma unroll
-            for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c], jscale);
+            for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c]);
         }
 }
 
 template <int ORDER, bool HAS_Z, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_push(GridView g, SpeciesView s, float jscale, float jinv)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_push(GridView g, SpeciesView s, float jscale,
+                                                                                  float jinv, int apar, int wpar)
 {
     using T = Tile<ORDER>;
-    __shared__ float fE[3][T::GN];
-    __shared__ float fB[3][T::GN];
-    __shared__ unsigned long long tJ[3 * T::JN];
-    __shared__ int s_holes, s_queue;
+    __shared__ __align__(16) unsigned char smem[T::SMEM];
+    float(*fE)[T::GN] = reinterpret_cast<float(*)[T::GN]>(smem);
+    float(*fB)[T::GN] = reinterpret_cast<float(*)[T::GN]>(smem + 3 * T::GN * 4);
+    unsigned long long* tJ = reinterpret_cast<unsigned long long*>(smem + 6 * T::GN * 4);
+    __shared__ int s_holes, s_queue, s_cnt[3];
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
+    // arrivals of the previous step first (frames dense again before pushing)
+    if (apar >= 0) fill_supercell<NT>(g, s, sc, apar, reinterpret_cast<int*>(smem), s_cnt);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
@@ -191,11 +208,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int n = s.count[sc];
     const int64_t base = (int64_t)sc * s.cap;
     const int64_t qbase = (int64_t)sc * g.qcap;
-    const int64_t qstride = (int64_t)g.nsc * g.qcap;
     const float dt = g.dt;
     const float cdx = dt / g.dx, cdy = dt / g.dy, cdz = dt / g.dz;
     const float inv_dvdt = 1.0f / (g.dx * g.dy * g.dz * dt);
-    const float jcx = -g.dx * inv_dvdt, jcy = -g.dy * inv_dvdt, jcz = -g.dz * inv_dvdt;
+    // current coefficients with the fixed-point scale folded in
+    const float jcx = -g.dx * inv_dvdt * jscale, jcy = -g.dy * inv_dvdt * jscale, jcz = -g.dz * inv_dvdt * jscale;
     const float qm = 0.5f * dt / s.mass;
     bool bad = false;
 
@@ -229,12 +246,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int inx = shape_weights<ORDER>(x0, wnx), isx = shape_weights<ORDER>(x0 - 0.5f, wsx);
         const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<ORDER>(y0 - 0.5f, wsy);
         const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<ORDER>(z0 - 0.5f, wsz);
-        const float Ex = interp<ORDER>(fE[0], isx, iny, inz, wsx, wny, wnz);
-        const float Ey = interp<ORDER>(fE[1], inx, isy, inz, wnx, wsy, wnz);
-        const float Ez = interp<ORDER>(fE[2], inx, iny, isz, wnx, wny, wsz);
-        const float Bx = interp<ORDER>(fB[0], inx, isy, isz, wnx, wsy, wsz) + g.b0x;
-        const float By = interp<ORDER>(fB[1], isx, iny, isz, wsx, wny, wsz) + g.b0y;
-        const float Bz = interp<ORDER>(fB[2], isx, isy, inz, wsx, wsy, wnz) + g.b0z;
+        // tile index of the node-centred first node; the staggered components
+        // differ from it by one node at most per axis (the guard offset is 1)
+        const int bn = ((inz + 1) * T::GY + (iny + 1)) * T::GX + (inx + 1);
+        const int ox_ = isx - inx, oy_ = (isy - iny) * T::GX, oz_ = (isz - inz) * (T::GX * T::GY);
+        const float Ex = interp<ORDER>(&fE[0][bn + ox_], wsx, wny, wnz);
+        const float Ey = interp<ORDER>(&fE[1][bn + oy_], wnx, wsy, wnz);
+        const float Ez = interp<ORDER>(&fE[2][bn + oz_], wnx, wny, wsz);
+        const float Bx = interp<ORDER>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
+        const float By = interp<ORDER>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
+        const float Bz = interp<ORDER>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
 
         // ---- relativistic Boris: half kick, rotation, half kick
         const float h = q * qm;
@@ -274,9 +295,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 DSz[k] = w1z[k] - wnz[k];
             }
             deposit<ORDER, T::NP>(tJ, inx + T::JL, iny + T::JL, inz + T::JL, wnx, DSx, wny, DSy, wnz, DSz,
-                                  jcx * qw, jcy * qw, jcz * qw, jscale);
+                                  jcx * qw, jcy * qw, jcz * qw);
         }
-        // queue the others (contiguous slots per wave from one LDS atomic)
+        // queue the others (contiguous slots per wave from one LDS atomic);
+        // one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 -
         const unsigned long long qmask = __ballot(!same);
         if (qmask) {
             const int leader = __ffsll((long long)qmask) - 1;
@@ -284,10 +306,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
             qb = __shfl(qb, leader, 64);
             if (!same) {
-                const int64_t e = qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull));
-                g.qbuf[e] = x0; g.qbuf[e + qstride] = y0; g.qbuf[e + 2 * qstride] = z0;
-                g.qbuf[e + 3 * qstride] = x1; g.qbuf[e + 4 * qstride] = y1; g.qbuf[e + 5 * qstride] = z1;
-                g.qbuf[e + 6 * qstride] = qw;
+                float4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
+                e[0] = make_float4(x0, y0, z0, qw);
+                e[1] = make_float4(x1, y1, z1, 0.0f);
             }
         }
 
@@ -324,15 +345,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // ---- queued particles: general (ORDER+2)-node window, all lanes busy
     const int nq = s_queue;
     for (int t = tid; t < nq; t += NT) {
-        const int64_t e = qbase + t;
-        const float x0 = g.qbuf[e], y0 = g.qbuf[e + qstride], z0 = g.qbuf[e + 2 * qstride];
-        const float x1 = g.qbuf[e + 3 * qstride], y1 = g.qbuf[e + 4 * qstride], z1 = g.qbuf[e + 5 * qstride];
-        const float qw = g.qbuf[e + 6 * qstride];
+        const float4* e = g.qbuf + 2 * (qbase + t);
+        const float4 a = e[0], b = e[1];
+        const float x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
+        const float x1 = b.x, y1 = b.y, z1 = b.z;
         float S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
         const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + T::JL;
         const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
         const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
-        deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw, jscale);
+        deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw);
     }
 
     // ---- hand the leavers to their destination supercells' arrival lists
@@ -349,9 +370,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         dy_ += (dy_ < 0) ? g.ncy : 0; dy_ -= (dy_ >= g.ncy) ? g.ncy : 0;
         dz_ += (dz_ < 0) ? g.ncz : 0; dz_ -= (dz_ >= g.ncz) ? g.ncz : 0;
         const int dest = dx_ + g.ncx * (dy_ + g.ncy * dz_);
-        const int k = atomicAdd(&s.in_count[dest], 1);
+        const int k = atomicAdd(&s.in_count[wpar * g.nsc + dest], 1);
         if (k < s.cap_in) {
-            const int64_t q_ = (int64_t)dest * s.cap_in + k;
+            const int64_t q_ = inbox_index(s, g.nsc, wpar, dest, k);
             // shift into the destination's frame; x - (-8) can round up onto the far face
             s.ix[q_] = fminf(x1 - (float)(mvx * SX), XMAX);
             s.iy[q_] = fminf(y1 - (float)(mvy * SY), YMAX);
@@ -387,20 +408,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, hipStream_t st)
+hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, int apar, int wpar,
+                       hipStream_t st)
 {
     if (s.cap > g.qcap) return hipErrorInvalidValue;  // the deposit queue must hold a full supercell
+    if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
     const dim3 grid(g.nsc);
     const bool hz = s.zs != nullptr;
     // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
     const float jscale = vmax > 0.0f ? 1073741824.0f / vmax : 1.0f;
     const float jinv = 1.0f / jscale;
     if (order == 1) {
-        if (hz) hipLaunchKernelGGL((k_push<1, true, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv);
-        else hipLaunchKernelGGL((k_push<1, false, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv);
+        if (hz) hipLaunchKernelGGL((k_push<1, true, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<1, false, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
     } else {
-        if (hz) hipLaunchKernelGGL((k_push<2, true, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv);
-        else hipLaunchKernelGGL((k_push<2, false, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv);
+        if (hz) hipLaunchKernelGGL((k_push<2, true, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<2, false, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
     }
     return hipGetLastError();
 }

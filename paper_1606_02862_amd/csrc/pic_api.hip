@@ -192,9 +192,9 @@ int alloc_species(pic_ctx* c, int s)
     v.cap = cap_ppc * SC_CELLS;
     int cap_in = v.cap / 4;
     cap_in = std::max(cap_in, 256);
-    cap_in = std::min(cap_in, MAX_MIGRATE);
+    cap_in = std::min(cap_in, c->order == 1 ? 2048 : MAX_MIGRATE);  // what the particle kernel's LDS can absorb
     v.cap_in = cap_in;
-    const size_t n = (size_t)nsc * v.cap, ni = (size_t)nsc * cap_in;
+    const size_t n = (size_t)nsc * v.cap, ni = (size_t)2 * nsc * cap_in;  // two step parities
     float** fl[] = {&v.x, &v.y, &v.z, &v.ux, &v.uy, &v.uz, &v.w};
     for (float** f : fl)
         if (!(*f = (float*)dev_alloc(c, n * 4))) return fail(c, PIC_ERR_OOM, "species %d: frames", s);
@@ -211,12 +211,12 @@ int alloc_species(pic_ctx* c, int s)
     if (!(v.iid = (uint32_t*)dev_alloc(c, ni * 4))) return fail(c, PIC_ERR_OOM, "species %d: arrivals", s);
     if (!(v.holes = (int32_t*)dev_alloc(c, ni * 4))) return fail(c, PIC_ERR_OOM, "species %d: holes", s);
     if (!(v.count = (int32_t*)dev_alloc(c, (size_t)nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
-    if (!(v.in_count = (int32_t*)dev_alloc(c, (size_t)nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
+    if (!(v.in_count = (int32_t*)dev_alloc(c, (size_t)2 * nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
     if (!(v.hole_count = (int32_t*)dev_alloc(c, (size_t)nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
     v.charge = (float)d.charge;
     v.mass = (float)d.mass;
     HIPCHK(c, launch_zero_i32(v.count, nsc, c->stream));
-    HIPCHK(c, launch_zero_i32(v.in_count, nsc, c->stream));
+    HIPCHK(c, launch_zero_i32(v.in_count, 2 * nsc, c->stream));
     HIPCHK(c, launch_zero_i32(v.hole_count, nsc, c->stream));
     return PIC_OK;
 }
@@ -442,7 +442,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     // one deposit queue shared by the species (their particle kernels run one after another)
     g.qcap = 0;
     for (int s = 0; s < n_species; ++s) g.qcap = std::max(g.qcap, c->sp[s].v.cap);
-    if (!(g.qbuf = (float*)dev_alloc(c, (size_t)7 * g.nsc * g.qcap * 4))) {
+    if (!(g.qbuf = (float4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(float4)))) {
         c->err = "device allocation of the deposit queue failed";
         return bail(PIC_ERR_OOM);
     }
@@ -497,16 +497,19 @@ int pic_step(pic_ctx* c, int n)
             HIPCHK(c, hipEventRecord(e0, c->stream));
         }
         HIPCHK(c, launch_zero_f32(c->g.J, 3 * N, c->stream));
+        // step `it` writes its leavers to parity it & 1 and absorbs the previous step's
+        const int wpar = it & 1, apar = it > 0 ? ((it - 1) & 1) : -1;
         for (int s = 0; s < c->nsp; ++s) {
             if (!c->sp[s].desc.mobile) continue;
-            HIPCHK(c, launch_push(c->g, c->sp[s].v, c->order, (float)push_vmax(c, s), c->stream));
+            HIPCHK(c, launch_push(c->g, c->sp[s].v, c->order, (float)push_vmax(c, s), apar, wpar, c->stream));
             c->pending_launches += c->timing ? 1 : 0;
         }
         if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
-        for (int s = 0; s < c->nsp; ++s) {
-            if (!c->sp[s].desc.mobile) continue;
-            HIPCHK(c, launch_migrate(c->g, c->sp[s].v, c->stream));
-        }
+        if (it == n - 1)  // last step of the call: leave the frames dense
+            for (int s = 0; s < c->nsp; ++s) {
+                if (!c->sp[s].desc.mobile) continue;
+                HIPCHK(c, launch_migrate(c->g, c->sp[s].v, wpar, c->stream));
+            }
         if (c->timing) HIPCHK(c, hipEventRecord(e2, c->stream));
         HIPCHK(c, launch_yee_b(c->g, 0.5f * dt, c->stream));
         HIPCHK(c, launch_yee_e(c->g, dt, c->stream));

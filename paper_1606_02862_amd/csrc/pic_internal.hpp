@@ -34,7 +34,7 @@ struct GridView {
     float* B;
     float* J;
     int32_t* flags;
-    float* qbuf;           // deposit queue: 7 arrays of nsc * qcap (x0,y0,z0,x1,y1,z1,qw)
+    float4* qbuf;          // deposit queue: nsc * qcap records of 2 float4 (x0,y0,z0,qw | x1,y1,z1,-)
     int qcap;              // queue slots per supercell (>= every species' frame capacity)
 };
 
@@ -46,11 +46,11 @@ struct SpeciesView {
     uint8_t* zs;            // charge state, or nullptr
     int32_t* count;         // particles per supercell
     int cap;                // slots per supercell (multiple of 256)
-    // migration buffers: per destination supercell, cap_in slots
+    // arrival lists: per step parity and destination supercell, cap_in slots
     float *ix, *iy, *iz, *iux, *iuy, *iuz, *iw;
     uint32_t* iid;
     uint8_t* izs;
-    int32_t* in_count;      // arrivals per supercell
+    int32_t* in_count;      // arrivals per parity and supercell (2 * nsc)
     int32_t* holes;         // per source supercell: vacated slots
     int32_t* hole_count;
     int cap_in;
@@ -86,8 +86,11 @@ hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 // vmax: upper bound of |q w| max(dx,dy,dz) / (dV dt) over the species' particles
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, hipStream_t st);
-hipError_t launch_migrate(const GridView& g, const SpeciesView& s, hipStream_t st);
+// apar: parity of the arrivals to absorb first (-1: none); wpar: parity the
+// leavers of this step are written to
+hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, int apar, int wpar,
+                       hipStream_t st);
+hipError_t launch_migrate(const GridView& g, const SpeciesView& s, int par, hipStream_t st);
 hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st);
 hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st);
 

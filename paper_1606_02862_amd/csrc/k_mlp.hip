@@ -38,161 +38,251 @@ __device__ inline float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// ln nu_prior = ln(n_e vbar a q / (P kT)) - z + ln ln(1 + 1/z), z = P / kT (FP32)
-__device__ inline float ln_prior(float kT, float ne, float P, float q)
-{
-    const float z = P / kT;
-    const float vbar = (float)C_CM_S * sqrtf(8.0f * kT / ((float)M_PI * (float)ME_C2_EV));
-    return logf(ne) + logf(vbar) + logf((float)LOTZ_A * q / (P * kT)) - z + logf(log1pf(1.0f / z));
-}
-
-// The 8 parameters of one network slice a lane needs for a forward tile.
-struct LaneWeights {
-    bf16x8 w2[4][2];   // B operands: W2[16t + l%16][32s + 8(l/16) + j]
-    float b2[4], w3[4];
+// Per charge state z: P_z, and the constant of the analytic prior
+// ln nu_prior = ln(n_e vbar a q / (P kT)) - P/kT + ln ln(1 + kT/P), with
+// vbar = c sqrt(8 kT / (pi m_e c^2)):  c_z = ln(c sqrt(8 / (pi m_e c^2)) a q_z / P_z).
+struct PriorTab {
+    float P[PIC_MAX_ZSTATES], invP[PIC_MAX_ZSTATES], c[PIC_MAX_ZSTATES];
 };
 
-__device__ inline void load_lane_weights(const float* P, int lane, LaneWeights& lw)
+__device__ inline void fill_prior(const IonTables& tab, PriorTab& T)
+{
+    const int z = threadIdx.x;
+    if (z < PIC_MAX_ZSTATES) {
+        const double P = z < tab.z_max ? tab.P[z] : 1.0, q = z < tab.z_max ? tab.q[z] : 1.0;
+        T.P[z] = (float)P;
+        T.invP[z] = (float)(1.0 / P);
+        T.c[z] = (float)log(C_CM_S * sqrt(8.0 / (M_PI * ME_C2_EV)) * LOTZ_A * q / P);
+    }
+}
+
+// Network inputs x0 = (log10 kT - 2) / 2, x1 = (log10 n_e - 21) / 2 and the
+// prior, in FP32 from the hardware base-2 logarithm; ln(1 + u) by the
+// identity ln(1 + u) = u ln(w) / (w - 1), w = fl(1 + u), which keeps full
+// relative accuracy for small u.
+__device__ inline void inputs_prior(float kT, float ne, const PriorTab& T, int z, float& x0, float& x1, float& prior)
+{
+    constexpr float LN2 = 0.693147180559945309f, HALF_LOG10_2 = 0.150514997831990598f;
+    const float l2t = __log2f(kT), l2n = __log2f(ne);
+    x0 = fmaf(l2t, HALF_LOG10_2, -1.0f);
+    x1 = fmaf(l2n, HALF_LOG10_2, -10.5f);
+    const float u = kT * T.invP[z];
+    const float w = 1.0f + u;
+    const float l1p = w == 1.0f ? u : u * (LN2 * __log2f(w)) / (w - 1.0f);
+    prior = LN2 * (l2n - 0.5f * l2t + __log2f(l1p)) + T.c[z] - T.P[z] / kT;
+}
+
+// Inference layout: the network runs transposed, hidden units as MFMA rows
+// and 16 samples as columns, so that each layer's result tile (D[h][n]: lane
+// n + 16*(h/4) of 16-row tile t holds hidden 16t + 4*(h/4) + e, e = 0..3) is
+// already the next layer's B operand once its K index is relabelled.  A lane
+// of group g = lane/16 holds, for K step s, the hidden units
+//   kperm(s, g, j) = 32s + 16*(j/4) + 4g + j%4,   j = 0..7,
+// and the weights of the next layer are loaded with the same relabelling (a
+// contraction does not depend on the order of its K index).
+__device__ inline int kperm(int s, int g, int j) { return 32 * s + 16 * (j >> 2) + 4 * g + (j & 3); }
+
+// Layer 1 runs on a 16x16x16 MFMA with an augmented K of 16.  The inputs x0
+// and x1 enter as two BF16 parts each (hi + mid carry 16 significant bits,
+// well below the BF16 resolution of the activations), in the order x0_hi,
+// x1_hi, x0_mid, x1_mid; then the six one-hot charge-state columns; then b1
+// as three BF16 parts against a constant input of 1; then three zero columns.
+// Every part is multiplied exactly by its BF16 weight, so layer 1 is the
+// product of BF16 weights with the FP32 inputs plus the FP32 bias, up to the
+// order of the FP32 sums.
+__device__ inline float w1_aug(const float* P, int h, int k)
+{
+    if (k < 4) return bf16r(P[OFF_W1 + h * NIN + (k & 1)]);
+    if (k < 10) return bf16r(P[OFF_W1 + h * NIN + 2 + (k - 4)]);
+    if (k > 12) return 0.0f;
+    const float b = P[OFF_B1 + h];
+    const float hi = bf16r(b), mid = bf16r(b - hi), lo = bf16r(b - hi - mid);
+    return k == 10 ? hi : (k == 11 ? mid : lo);
+}
+
+// The network slices one lane holds in registers (lane = c + 16g).
+struct Net {
+    bf16x4 a1[4];      // layer 1 A operand: row 16t + c, K columns 4g..4g+3 of the augmented W1
+    bf16x8 a2[4][2];   // layer 2 A operand: W2[16t + c][kperm(s, g, j)]
+    bf16x8 a3[2];      // head A operand: W3[kperm(s, g, j)] in rows c = 0, 4, 8, 12, zero elsewhere
+    floatx4 b2[4];     // layer 2 bias in the result layout: b2[16t + 4g + e]
+    float b3;
+    // input column of group g (K rows 4g..4g+3) for charge state z:
+    // (0x3F80 << 16 (z - zbase) if 0 <= z - zbase < 4) | cbits, BF16 1.0 = 0x3F80
+    int zbase;
+    uint64_t cbits;
+};
+
+__device__ inline void load_net(const float* P, int lane, Net& n)
 {
     const int g = lane >> 4, c = lane & 15;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
 #pragma unroll
+        for (int e = 0; e < 4; ++e) n.a1[t][e] = (__bf16)w1_aug(P, 16 * t + c, 4 * g + e);
+#pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) lw.w2[t][s][j] = (__bf16)P[OFF_W2 + (16 * t + c) * NH + 32 * s + 8 * g + j];
-        lw.b2[t] = P[OFF_B2 + 16 * t + c];
-        lw.w3[t] = bf16r(P[OFF_W3 + 16 * t + c]);
+            for (int j = 0; j < 8; ++j) n.a2[t][s][j] = (__bf16)P[OFF_W2 + (16 * t + c) * NH + kperm(s, g, j)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) n.b2[t][e] = P[OFF_B2 + 16 * t + 4 * g + e];
     }
-}
-
-// Layer 1 column table in LDS: c1[z][k] = W1[k][2+z] + b1[k] (z < 6), and the
-// two continuous columns, all BF16-rounded weights.
-struct L1Table {
-    float wx0[NH], wx1[NH], cz[6][NH];
-};
-
-__device__ inline void fill_l1(const float* P, L1Table& T)
-{
-    for (int k = threadIdx.x; k < NH; k += blockDim.x) {
-        T.wx0[k] = bf16r(P[OFF_W1 + k * NIN + 0]);
-        T.wx1[k] = bf16r(P[OFF_W1 + k * NIN + 1]);
-        for (int z = 0; z < 6; ++z) T.cz[z][k] = bf16r(P[OFF_W1 + k * NIN + 2 + z]) + P[OFF_B1 + k];
-    }
-}
-
-// Forward of 16 samples held by the wave: lane l supplies sample l%16's
-// (x0, x1, z).  Returns y for sample (4*(l/16) + r) in out[r] (all lanes of a
-// row group hold the same four values).
-__device__ inline void forward_tile(const L1Table& T, const LaneWeights& lw, float b3, int lane, float x0, float x1, int z,
-                                    float out[4])
-{
-    const int g = lane >> 4;
-    bf16x8 a[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 32 * s + 8 * g + j;
-            const float zz = fmaf(T.wx0[k], x0, fmaf(T.wx1[k], x1, T.cz[z][k]));
-            a[s][j] = (__bf16)silu(zz);
-        }
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 8; ++j) n.a3[s][j] = (__bf16)((c & 3) == 0 ? P[OFF_W3 + kperm(s, g, j)] : 0.0f);
+    n.b3 = P[OFF_B3];
+    n.zbase = g == 1 ? 0 : (g == 2 ? 4 : 64);                  // one-hot columns 0..3 and 4..5
+    n.cbits = g == 2 ? 0x3F803F8000000000ull : (g == 3 ? 0x3F80ull : 0ull);  // b1 hi, mid | b1 lo
+}
+
+// SiLU of a result tile pair, packed as the next layer's B operand for K step s.
+__device__ inline bf16x8 silu_pack(const floatx4& lo, const floatx4& hi)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        r[e] = (__bf16)silu(lo[e]);
+        r[4 + e] = (__bf16)silu(hi[e]);
+    }
+    return r;
+}
+
+// Forward of 16 samples: lane c + 16g supplies sample c's inputs (the packed
+// BF16 pairs (x0_hi, x1_hi) and (x0_mid, x1_mid), and the charge state z;
+// every group the same sample).  Returns y of sample c in every lane of
+// column c.
+__device__ inline float forward16(const Net& n, int g, uint32_t xhi, uint32_t xmid, int z)
+{
+    const unsigned d = (unsigned)(z - n.zbase);
+    const uint64_t onehot = d < 4u ? (0x3F80ull << (16u * d)) : 0ull;
+    const uint64_t col = g == 0 ? ((uint64_t)xmid << 32 | xhi) : (onehot | n.cbits);
+    bf16x4 xb;
+    __builtin_memcpy(&xb, &col, 8);
+    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+    floatx4 d1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d1[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(n.a1[t], xb, zero, 0, 0, 0);
+    const bf16x8 h1a = silu_pack(d1[0], d1[1]), h1b = silu_pack(d1[2], d1[3]);
+    floatx4 d2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        floatx4 d = {0.f, 0.f, 0.f, 0.f};
-        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], lw.w2[t][0], d, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], lw.w2[t][1], d, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = fmaf(lw.w3[t], bf16r(silu(d[r] + lw.b2[t])), acc[r]);
+        d2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[t][0], h1a, n.b2[t], 0, 0, 0);
+        d2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[t][1], h1b, d2[t], 0, 0, 0);
     }
+    const bf16x8 h2a = silu_pack(d2[0], d2[1]), h2b = silu_pack(d2[2], d2[3]);
+    floatx4 d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[0], h2a, zero, 0, 0, 0);
+    d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[1], h2b, d3, 0, 0, 0);
+    return d3[0] + n.b3;  // row 4g of the head tile: y of sample c
+}
+
+// BF16 hi and mid parts of (x0, x1), packed as (x0, x1) pairs.
+__device__ inline void split_inputs(float x0, float x1, uint32_t& hi, uint32_t& mid)
+{
+    const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
+    const __bf16 m0 = (__bf16)(x0 - (float)h0), m1 = (__bf16)(x1 - (float)h1);
+    uint16_t a, b, c, e;
+    __builtin_memcpy(&a, &h0, 2); __builtin_memcpy(&b, &h1, 2);
+    __builtin_memcpy(&c, &m0, 2); __builtin_memcpy(&e, &m1, 2);
+    hi = (uint32_t)a | (uint32_t)b << 16;
+    mid = (uint32_t)c | (uint32_t)e << 16;
+}
+
+// Forward of the 64 samples a wave holds, one per lane (z < 0: no sample).
+// Sub-tile q takes the samples of lanes 16q..16q+15; its result for sample
+// 16q + c lands in lane c + 16g for every g, so lane 16q + c reads its own.
+__device__ inline float forward64(const Net& n, int lane, float x0, float x1, int z)
+{
+    const int g = lane >> 4;
+    uint32_t xhi, xmid;
+    split_inputs(x0, x1, xhi, xmid);
+    float y = 0.0f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float v = acc[r];
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 8, 64);
-        out[r] = v + b3;
+    for (int q = 0; q < 4; ++q) {
+        const int src = 16 * q + (lane & 15);
+        const int zq = __shfl(z, src, 64);
+        if (__ballot(zq >= 0) == 0) continue;  // wave-uniform: the 16 samples are the same in every group
+        const uint32_t hq = (uint32_t)__shfl((int)xhi, src, 64), mq = (uint32_t)__shfl((int)xmid, src, 64);
+        const float yq = forward16(n, g, hq, mq, zq);
+        if (g == q) y = yq;
     }
+    return y;
 }
 
 // ---------------------------------------------------------------- inference
+// Exact FP64 rate for the (rare) samples outside the trained range, kept out
+// of line so that its register footprint does not lower the occupancy of the
+// surrogate path.
+__device__ __noinline__ double fallback_rate(double kT, double ne, double P, double q, const double* glx,
+                                            const double* glw)
+{
+    return rate_exact(kT, ne, P, q, glx, glw);
+}
+
 struct MlpArgs {
     const float* params;
     float mu, s;
     float t_min, t_max, n_min, n_max;  // trained range (eV, cm^-3)
 };
 
-__device__ inline float x0_of(float kT) { return (log10f(kT) - 2.0f) * 0.5f; }
-__device__ inline float x1_of(float ne) { return (log10f(ne) - 21.0f) * 0.5f; }
 
 // Per supercell of ions: nu[p] for every ion (0 for Z >= z_max); out-of-range
 // inputs take the exact FP64 quadrature.  counters[0] += active ions,
-// counters[2] += fallbacks.
+// counters[2] += fallbacks.  Persistent workgroups (weights loaded once); a
+// wave takes 64 ions of a supercell at a time, one per lane.
 __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion, IonTables tab, MlpArgs m,
                                                     const double* ne, const double* kT, double* nu, const double* gl,
                                                     unsigned long long* counters)
 {
-    __shared__ L1Table T;
     __shared__ double glx[GL_NODES], glw[GL_NODES];
+    __shared__ PriorTab PT;
     __shared__ int s_active, s_fallback;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    fill_l1(m.params, T);
     if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
+    fill_prior(tab, PT);
     if (tid == 0) { s_active = 0; s_fallback = 0; }
-    LaneWeights lw;
-    load_lane_weights(m.params, lane, lw);
-    const float b3 = m.params[OFF_B3];
+    Net net;
+    load_net(m.params, lane, net);
     __syncthreads();
-    const int sc = blockIdx.x;
-    const int n = ion.count[sc];
-    const int64_t base = (int64_t)sc * ion.cap;
-    const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     int active = 0, fallback = 0;
-    const int ntile = (n + 15) / 16;
-    for (int tile = wave; tile < ntile; tile += BLOCK / 64) {
-        // lane l%16 reads sample 16*tile + l%16 (every row group reads the same 16)
-        const int t = 16 * tile + (lane & 15);
-        float x0 = 0.f, x1 = 0.f, fkT = 1.f, fne = 1.f;
-        int Z = 0;
-        bool act = false, inr = false;
-        double dkT = 0.0, dne = 0.0;
-        int64_t p = 0;
-        if (t < n) {
-            p = base + t;
-            Z = ion.zs[p];
-            act = Z < tab.z_max;
-            const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
-                               (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
-            dkT = kT[gi];
-            dne = ne[gi];
-            fkT = (float)dkT;
-            fne = (float)dne;
-            inr = act && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min && fne <= m.n_max;
-            if (inr) { x0 = x0_of(fkT); x1 = x1_of(fne); }
-        }
-        float y[4];
-        forward_tile(T, lw, b3, lane, x0, x1, inr ? Z : 0, y);
-        // lane l (< 16) finishes sample 16*tile + l: its y lives in row group l/4, slot l%4
-        const int src = 16 * (lane >> 2);
-        float yv = __shfl(y[0], src, 64), y1v = __shfl(y[1], src, 64), y2v = __shfl(y[2], src, 64),
-              y3v = __shfl(y[3], src, 64);
-        const int r = lane & 3;
-        const float ys = r == 0 ? yv : (r == 1 ? y1v : (r == 2 ? y2v : y3v));
-        if (lane < 16 && t < n) {
-            double v = 0.0;
-            if (act) {
-                ++active;
+    for (int sc = blockIdx.x; sc < g.nsc; sc += gridDim.x) {
+        const int n = ion.count[sc];
+        const int64_t base = (int64_t)sc * ion.cap;
+        const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
+        for (int t = 64 * wave + lane; t - lane < n; t += BLOCK) {
+            float x0 = 0.f, x1 = 0.f, prior = 0.f;
+            int Z = 0, zin = -1;
+            bool act = false, inr = false;
+            double dkT = 0.0, dne = 0.0;
+            const int64_t p = base + t;
+            if (t < n) {
+                Z = ion.zs[p];
+                act = Z < tab.z_max;
+                const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
+                                   (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
+                dkT = kT[gi];
+                dne = ne[gi];
+                const float fkT = (float)dkT, fne = (float)dne;
+                inr = act && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min && fne <= m.n_max;
                 if (inr) {
-                    const float lnv = ln_prior(fkT, fne, (float)tab.P[Z], (float)tab.q[Z]) + m.mu + m.s * ys;
-                    v = exp((double)lnv);
-                } else {
-                    ++fallback;
-                    v = rate_exact(dkT, dne, tab.P[Z], tab.q[Z], glx, glw);
+                    inputs_prior(fkT, fne, PT, Z, x0, x1, prior);
+                    zin = Z;
                 }
             }
-            nu[p] = v;
+            const float y = forward64(net, lane, x0, x1, zin);
+            if (t < n) {
+                double v = 0.0;
+                if (act) {
+                    ++active;
+                    if (inr) {
+                        v = (double)__expf(prior + m.mu + m.s * y);  // ln nu <= ~40 on the trained range
+                    } else {
+                        ++fallback;
+                        v = fallback_rate(dkT, dne, tab.P[Z], tab.q[Z], glx, glw);
+                    }
+                }
+                nu[p] = v;
+            }
         }
     }
     atomicAdd(&s_active, active);
@@ -209,7 +299,8 @@ hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonT
                            unsigned long long* counters, hipStream_t st)
 {
     MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
-    hipLaunchKernelGGL(k_rate_mlp, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, gl, counters);
+    const int blocks = g.nsc < 1024 ? g.nsc : 1024;
+    hipLaunchKernelGGL(k_rate_mlp, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, gl, counters);
     return hipGetLastError();
 }
 
@@ -217,41 +308,35 @@ hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonT
 __global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Zs,
                                                        IonTables tab, MlpArgs m, const double* gl, double* out)
 {
-    __shared__ L1Table T;
     __shared__ double glx[GL_NODES], glw[GL_NODES];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    fill_l1(m.params, T);
+    __shared__ PriorTab PT;
+    const int tid = threadIdx.x, lane = tid & 63;
     if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
-    LaneWeights lw;
-    load_lane_weights(m.params, lane, lw);
-    const float b3 = m.params[OFF_B3];
+    fill_prior(tab, PT);
+    Net net;
+    load_net(m.params, lane, net);
     __syncthreads();
-    const int64_t ntile = (n + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * (BLOCK / 64) + wave; tile < ntile; tile += (int64_t)gridDim.x * (BLOCK / 64)) {
-        const int64_t i = 16 * tile + (lane & 15);
-        float x0 = 0.f, x1 = 0.f, fkT = 1.f, fne = 1.f;
-        int Z = 0;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + tid; i - lane < n; i += stride) {
+        float x0 = 0.f, x1 = 0.f, prior = 0.f;
+        int Z = -1, zin = -1;
         bool inr = false;
         if (i < n) {
             Z = Zs[i];
-            fkT = (float)kT[i];
-            fne = (float)ne[i];
+            const float fkT = (float)kT[i], fne = (float)ne[i];
             inr = Z >= 0 && Z < tab.z_max && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min &&
                   fne <= m.n_max;
-            if (inr) { x0 = x0_of(fkT); x1 = x1_of(fne); }
-        }
-        float y[4];
-        forward_tile(T, lw, b3, lane, x0, x1, inr ? Z : 0, y);
-        const int src = 16 * (lane >> 2);
-        float yv = __shfl(y[0], src, 64), y1v = __shfl(y[1], src, 64), y2v = __shfl(y[2], src, 64),
-              y3v = __shfl(y[3], src, 64);
-        const int r = lane & 3;
-        const float ys = r == 0 ? yv : (r == 1 ? y1v : (r == 2 ? y2v : y3v));
-        if (lane < 16 && i < n) {
             if (inr) {
-                out[i] = (double)(ln_prior(fkT, fne, (float)tab.P[Z], (float)tab.q[Z]) + m.mu + m.s * ys);
+                inputs_prior(fkT, fne, PT, Z, x0, x1, prior);
+                zin = Z;
+            }
+        }
+        const float y = forward64(net, lane, x0, x1, zin);
+        if (i < n) {
+            if (inr) {
+                out[i] = (double)(prior + m.mu + m.s * y);
             } else if (Z >= 0 && Z < tab.z_max) {
-                const double v = rate_exact(kT[i], ne[i], tab.P[Z], tab.q[Z], glx, glw);
+                const double v = fallback_rate(kT[i], ne[i], tab.P[Z], tab.q[Z], glx, glw);
                 out[i] = v > 0.0 ? log(v) : -INFINITY;
             } else {
                 out[i] = -INFINITY;
@@ -265,8 +350,8 @@ hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, con
 {
     if (n <= 0) return hipSuccess;
     MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
-    int64_t blocks = (n + 16 * (BLOCK / 64) - 1) / (16 * (BLOCK / 64));
-    if (blocks > 4096) blocks = 4096;
+    int64_t blocks = (n + BLOCK - 1) / BLOCK;
+    if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_ln_rate_mlp, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, kT, ne, Z, tab, m, gl, out);
     return hipGetLastError();
 }

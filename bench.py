@@ -33,7 +33,8 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "push_shear128_counters.json")
-PUSH_SOURCE = os.path.join(ROOT, "paper_1606_02862_amd", "csrc", "k_push.hip")
+PUSH_SOURCES = [os.path.join(ROOT, "paper_1606_02862_amd", "csrc", f)
+                for f in ("k_push.hip", "pic_migrate.hpp", "pic_device.hpp", "pic_internal.hpp")]
 
 
 def algorithmic_bytes_per_push(n_particles: int, n_cells: int, order: int) -> int:
@@ -50,9 +51,12 @@ def algorithmic_bytes_per_step(n_particles: int, n_cells: int) -> int:
     return algorithmic_bytes_per_push(n_particles, n_cells, 1) + n_cells * (12 + 3 * 36 + 12)
 
 
-def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(n_particles: int):
@@ -64,7 +68,7 @@ def traffic_from_profile(n_particles: int):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("k_push_sha256_16") != source_hash(PUSH_SOURCE) or d.get("particles") != n_particles:
+    if d.get("k_push_sha256_16") != source_hash(PUSH_SOURCES) or d.get("particles") != n_particles:
         return None
     fetch = d["fetch_kib_per_dispatch"] * 1024 / d["fetch_scale"]
     write = d["write_kib_per_dispatch"] * 1024 / d["write_scale"]

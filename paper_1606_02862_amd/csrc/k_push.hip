@@ -167,6 +167,19 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
         }
 }
 
+// Element at a 32-bit byte offset from a block-uniform base: lets the compiler
+// use the scalar-base + 32-bit-offset global addressing form.
+template <typename E>
+__device__ inline E& at(E* base, unsigned byte_off)
+{
+    return *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename E>
+__device__ inline const E& at(const E* base, unsigned byte_off)
+{
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 template <int ORDER, bool HAS_Z, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_push(GridView g, SpeciesView s, float jscale,
                                                                                   float jinv, int apar, int wpar)
@@ -216,29 +229,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const float qm = 0.5f * dt / s.mass;
     bool bad = false;
 
+    // this supercell's frames: block-uniform base pointers, 32-bit slot offsets
+    float* const px = s.x + base;
+    float* const py = s.y + base;
+    float* const pz = s.z + base;
+    float* const pux = s.ux + base;
+    float* const puy = s.uy + base;
+    float* const puz = s.uz + base;
+    const float* const pw = s.w + base;
+    const uint8_t* const pzs = HAS_Z ? s.zs + base : nullptr;
+
     // software pipeline: the next frame's particle is loaded while this one is computed
     float nx0 = 0.f, ny0 = 0.f, nz0 = 0.f, nux = 0.f, nuy = 0.f, nuz = 0.f, nw = 0.f;
     int nzs = 0;
     if (tid < n) {
-        const int64_t p = base + tid;
-        nx0 = s.x[p]; ny0 = s.y[p]; nz0 = s.z[p];
-        nux = s.ux[p]; nuy = s.uy[p]; nuz = s.uz[p]; nw = s.w[p];
-        if constexpr (HAS_Z) nzs = s.zs[p];
+        const unsigned u = 4u * (unsigned)tid;
+        nx0 = at(px, u); ny0 = at(py, u); nz0 = at(pz, u);
+        nux = at(pux, u); nuy = at(puy, u); nuz = at(puz, u); nw = at(pw, u);
+        if constexpr (HAS_Z) nzs = pzs[tid];
     }
     for (int f = 0; f < n; f += NT) {
         const int slot = f + tid;
         if (slot >= n) break;
-        const int64_t p = base + slot;
+        const unsigned u = 4u * (unsigned)slot;  // byte offset of the slot
         const float x0 = nx0, y0 = ny0, z0 = nz0;
         float ux = nux, uy = nuy, uz = nuz;
         const float wgt = nw;
         float q = s.charge;
         if constexpr (HAS_Z) q *= (float)nzs;
-        if (slot + NT < n) {
-            const int64_t pn = p + NT;
-            nx0 = s.x[pn]; ny0 = s.y[pn]; nz0 = s.z[pn];
-            nux = s.ux[pn]; nuy = s.uy[pn]; nuz = s.uz[pn]; nw = s.w[pn];
-            if constexpr (HAS_Z) nzs = s.zs[pn];
+        {   // unconditional (the last particle again past the end) so that no branch
+            // obscures the order of these loads relative to this iteration's stores
+            const int sn = slot + NT < n ? slot + NT : n - 1;
+            const unsigned un = 4u * (unsigned)sn;
+            nx0 = at(px, un); ny0 = at(py, un); nz0 = at(pz, un);
+            nux = at(pux, un); nuy = at(puy, un); nuz = at(puz, un); nw = at(pw, un);
+            if constexpr (HAS_Z) nzs = pzs[sn];
         }
 
         // ---- gather at node-centred and half-shifted positions per axis
@@ -315,8 +340,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // ---- store in place; a particle that left the supercell keeps its
         // unshifted position here and its slot goes on the hole list, handed
         // over after the frame loop so no wave waits on a global atomic here
-        s.x[p] = x1; s.y[p] = y1; s.z[p] = z1;
-        s.ux[p] = ux; s.uy[p] = uy; s.uz[p] = uz;
+        at(px, u) = x1; at(py, u) = y1; at(pz, u) = z1;
+        at(pux, u) = ux; at(puy, u) = uy; at(puz, u) = uz;
         const bool left = (x1 < 0.0f) || (x1 >= (float)SX) || (y1 < 0.0f) || (y1 >= (float)SY) || (z1 < 0.0f) ||
                           (z1 >= (float)SZ);
         const unsigned long long lmask = __ballot(left);
@@ -332,9 +357,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 } else {
                     // hole list full (reported through FLAG_MIGRATE below): keep the
                     // particle inside its supercell so every later access stays in bounds
-                    s.x[p] = fminf(fmaxf(x1, 0.0f), XMAX);
-                    s.y[p] = fminf(fmaxf(y1, 0.0f), YMAX);
-                    s.z[p] = fminf(fmaxf(z1, 0.0f), ZMAX);
+                    at(px, u) = fminf(fmaxf(x1, 0.0f), XMAX);
+                    at(py, u) = fminf(fmaxf(y1, 0.0f), YMAX);
+                    at(pz, u) = fminf(fmaxf(z1, 0.0f), ZMAX);
                 }
             }
         }

@@ -180,7 +180,7 @@ def main(argv=None):
     ap.add_argument("--config", type=int, default=1, help="workload preset (1: 128^3 CIC shear, 2: TSC e+p)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-box", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-ionize", action="store_true", help="skip the ionisation leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")

@@ -181,6 +181,41 @@ def test_mlp_gradient_matches_oracle_backprop(P):
         assert rel < 2e-2 and cos > 0.999, k
 
 
+def test_mlp_inference_matches_oracle_forward(P):
+    """The fused inference kernel (transposed MFMA layout, augmented layer-1 K,
+    head on MFMA) evaluates the same network as the oracle's plain FP64
+    forward.  With BF16 weights on both sides, the GPU differs only by BF16
+    rounding of the 128 activations (relative 2^-9 each), FP32 sums and the
+    FP32 prior; per sample, |d ln nu| must stay within s times the
+    first-order bound of the activation rounding propagated through W2, SiLU'
+    and W3, plus 1e-4 for the FP32 parts."""
+    cfg = _carbon_cfg((8, 8, 4))
+    r = workloads.rng(31)
+    p = mlp.init_params(5)
+    p["b1"] = r.uniform(-0.5, 0.5, 64)
+    p["b2"] = r.uniform(-0.5, 0.5, 64)
+    p["b3"] = np.array([0.3])
+    flat = _flat(p).astype(np.float32)
+    for k, (o, n) in {"W1": (0, 512), "W2": (576, 4096), "W3": (4736, 64)}.items():
+        flat[o:o + n] = _bf16(flat[o:o + n])
+    pref = _unflat(flat)
+    mu, s = -0.1, 0.5
+    T, ne, Z = workloads.loguniform_rate_inputs(32, 50000)
+    Pt, qt = workloads.CARBON_IONIZATION_EV, workloads.CARBON_LOTZ_Q
+    with P.Pic(cfg) as pic:
+        pic.mlp_set_params(1, flat, [mu, s], [1.0, 1e4, 1e19, 1e23])
+        got = pic.rate_eval("mlp", 1, T, ne, Z)
+    want = mlp.ln_rate(pref, mu, s, T, ne, Z, Pt, qt)
+    _, c = mlp.forward(pref, mlp.features(T, ne, Z))
+    dz2 = (np.abs(c["h1"]) * 2.0**-9) @ np.abs(pref["W2"]).T
+    bound = (np.abs(mlp.dsilu(c["z2"])) * dz2 + np.abs(c["h2"]) * 2.0**-9) @ np.abs(pref["W3"][0])
+    err = np.abs(got - want)
+    _print("inference vs oracle: max", err.max(), "median", np.median(err), "max err/bound",
+           (err / (s * bound + 1e-4)).max())
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= s * 1.1 * bound + 1e-4)
+
+
 @pytest.fixture(scope="module")
 def trained(P):
     """Train the surrogate on the GPU with the full recipe (1M samples)."""

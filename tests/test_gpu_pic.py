@@ -142,6 +142,34 @@ def test_migration_keeps_every_particle(P):
     assert m["gauss_max"] <= 1e-4 * m["rho_max"]
 
 
+def test_one_step_parity_ragged_and_empty_supercells(P):
+    """Electrons at random positions in part of the box only: one column of
+    supercells stays empty, the others hold random (ragged) counts with
+    partly filled last frames; the proton species has no particles at all.
+    Random non-zero E and B."""
+    cfg = workloads.reduced(2, 24, 16, 8)
+    g = oracle.grid_from_config(cfg)
+    r = workloads.rng(41)
+    n = 5000
+    x = r.uniform(0.0, 13.0, n)  # supercell columns 0 and 1 (partly); column 2 empty
+    e = oracle.Species(x, r.uniform(0, 16, n), r.uniform(0, 8, n), r.normal(0, 0.05, n), r.normal(0, 0.05, n),
+                       r.normal(0, 0.05, n), np.full(n, 0.125), np.arange(n, dtype=np.int64), q=-1.0, m=1.0)
+    z0 = np.zeros(0)
+    prot = oracle.Species(z0, z0, z0, z0, z0, z0, z0, np.zeros(0, dtype=np.int64), q=1.0,
+                          m=workloads.PROTON_MASS)
+    E, B = workloads.random_fields(42, 24, 16, 8, amp=0.05)
+    st = oracle.State(g, [e, prot], E, B, np.zeros_like(E), 0)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        counts = pic.moments()["count"]
+        err = parity.one_step_errors(pic, cfg, s0)
+        after = pic.moments()["count"]
+    _print("ragged/empty", counts, after, err)
+    assert counts[0] == n and counts[1] == 0 and after[0] == n and after[1] == 0
+    assert err["jmax"] > 0
+    assert err["u"][0] <= 1e-5 and err["J"] <= 1e-4 and err["x"][0] <= 2e-6
+
+
 # ---------------------------------------------------------------------------
 # full-size workload in the benchmark's configuration: sampled parity
 
@@ -170,6 +198,46 @@ def test_full_size_shear128_sampled_parity(P):
     _print("sampled momentum error", float((du / nu).max()), "gauss", m["gauss_max"], m["rho_max"])
     assert float((du / nu).max()) <= 1e-5
     assert m["count"][0] == 128**3 * 16
+    assert m["gauss_max"] <= 1e-4 * m["rho_max"]
+
+
+def test_full_size_ep256_tsc_sampled_parity(P):
+    """256x256x128 TSC, electrons + protons at 8 ppc each in B0 (134M
+    particles): sampled momenta and positions of both species against the
+    oracle's gather, Boris and move from the GPU's own pre-step state; Gauss
+    and particle counts over the run."""
+    cfg = workloads.config(2)
+    _print("full-size 256x256x128 TSC sampled parity")
+    g = oracle.grid_from_config(cfg)
+    nx, ny, nz = 256, 256, 128
+    with P.Pic(cfg) as pic:
+        pic.step(3)
+        E, B, _ = pic.get_fields()
+        pre = [pic.get_particles(i) for i in range(2)]
+        rng = workloads.rng(78)
+        idx = [rng.choice(p["id"].size, 1500, replace=False) for p in pre]
+        pre = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(pre, idx)]
+        pic.step(1)
+        post = [pic.get_particles(i) for i in range(2)]
+        post = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(post, idx)]
+        m = pic.moments()
+    E, B = E.astype(np.float64), B.astype(np.float64)
+    for sp, a, b in zip(cfg["species"], pre, post):
+        assert np.array_equal(a["id"], b["id"])
+        Ep, Bp = oracle.gather(g, E, B, a["x"], a["y"], a["z"])
+        ux, uy, uz = oracle.boris(sp["charge"] / sp["mass"], g.dt, Ep, Bp, a["ux"], a["uy"], a["uz"])
+        du = np.sqrt((b["ux"] - ux) ** 2 + (b["uy"] - uy) ** 2 + (b["uz"] - uz) ** 2)
+        eu = float((du / np.maximum(np.sqrt(ux**2 + uy**2 + uz**2), sp["u_th"])).max())
+        ig = 1.0 / np.sqrt(1.0 + ux**2 + uy**2 + uz**2)
+        ex = 0.0
+        for c, uc, n in (("x", ux, nx), ("y", uy, ny), ("z", uz, nz)):
+            want = np.mod(a[c] + g.dt * uc * ig, n)
+            d = np.abs(b[c] - want)
+            ex = max(ex, float(np.minimum(d, n - d).max()))
+        _print(sp["name"], "sampled momentum error", eu, "position error", ex)
+        assert eu <= 1e-5 and ex <= 4e-6
+    _print("gauss", m["gauss_max"], m["rho_max"], "counts", m["count"])
+    assert list(m["count"]) == [nx * ny * nz * 8, nx * ny * nz * 8]
     assert m["gauss_max"] <= 1e-4 * m["rho_max"]
 
 

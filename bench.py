@@ -177,7 +177,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=1, help="workload preset (1: 128^3 CIC shear, 2: TSC e+p)")
+    ap.add_argument("--config", type=int, default=1,
+                    help="workload preset (1: 128^3 CIC shear, 2: 256x256x128 TSC e+p, 5: 128^3 TSC KHI e+p)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-box", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=32)

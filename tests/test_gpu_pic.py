@@ -128,6 +128,38 @@ def test_energy_trace_100_steps(P):
     assert abs(ms[-1]["charge_total"]) < 1e-6 * ms[-1]["rho_max"] * 16**3
 
 
+def test_khi_magnetic_growth_tracks_oracle(P):
+    """The paper's Kelvin-Helmholtz workload (electrons + protons at 16 ppc
+    each, TSC, +-0.2c shear) on a 16x16x8 box: the magnetic energy grows by
+    orders of magnitude from particle noise, and the GPU's W_B trace follows
+    the oracle's step by step; total energy and Gauss's law hold."""
+    cfg = workloads.reduced(5, 16, 16, 8)
+    nsteps = 100
+    st = oracle.init_state(cfg)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        ref = s0.copy()
+        tr = oracle.step(ref, nsteps, trace=True)
+        ms = []
+        for _ in range(nsteps + 1):
+            ms.append(pic.moments())
+            if len(ms) <= nsteps:
+                pic.step(1)
+    wb = np.array([m["w_b"] for m in ms])[:nsteps]
+    wb_ref = tr[:, 1]
+    we = np.array([m["w_e"] for m in ms])
+    k = np.array([m["kinetic_total"] for m in ms])
+    t_gpu = we[:-1] + wb + 0.5 * (k[:-1] + k[1:])
+    t_ref = oracle.energy_trace_total(tr)
+    rel_b = np.abs(wb[1:] - wb_ref[1:]) / wb_ref[1:]
+    _print("W_B ref", wb_ref[[1, 10, 50, 99]], "gpu", wb[[1, 10, 50, 99]], "max rel", rel_b.max(),
+           "total max rel", (np.abs(t_gpu - t_ref) / t_ref).max())
+    assert wb_ref[99] > 100 * wb_ref[10] and wb[99] > 100 * wb[10]
+    assert rel_b.max() <= 1e-2
+    assert (np.abs(t_gpu - t_ref) / t_ref).max() <= 1e-3
+    assert ms[-1]["gauss_max"] <= 1e-4 * ms[-1]["rho_max"]
+
+
 def test_migration_keeps_every_particle(P):
     cfg = workloads.reduced(1, 16, 16, 8)
     with P.Pic(cfg) as pic:

@@ -71,11 +71,23 @@ def _config(idx):
                       rho_bg=0.0, shape="tsc", seed=SEED_BASE + idx, n_ref_cm3=1e21),
             species=[_electron(8, 0.02, cap_ppc=28), carbon], steps=100,
             rate_mode="mlp" if idx == 4 else "exact")
+    if idx == 5:
+        # the paper's benchmark: Kelvin-Helmholtz shear flow, electrons and ions
+        # at 16 ppc each, TSC; both species drift together in each layer (no
+        # net current), ions at the electrons' temperature
+        ion = dict(name="proton", charge=1.0, mass=PROTON_MASS, ppc=16, density=1.0,
+                   u_th=0.01 / PROTON_MASS ** 0.5, drift_beta=(0.2, 0.0, 0.0), layout="shear", mobile=True,
+                   coincident_with=0, z_init=0, z_max=0, ionization_ev=(), lotz_q=(), cap_ppc=None)
+        return dict(
+            name="khi128_tsc", workload="128^3 TSC Kelvin-Helmholtz shear flow +-0.2c, electrons + protons 16 ppc each",
+            grid=dict(nx=128, ny=128, nz=128, dx=1.0, dy=1.0, dz=1.0, dt=0.5, b0=(0.0, 0.0, 0.0),
+                      rho_bg=0.0, shape="tsc", seed=SEED_BASE + 5, n_ref_cm3=1e21),
+            species=[_electron(16, 0.01, (0.2, 0.0, 0.0), "shear"), ion], steps=1000)
     raise ValueError(f"no preset {idx}")
 
 
 def config(idx: int, **grid_overrides) -> dict:
-    """Preset `idx` (0..4); keyword arguments replace grid entries (e.g. a
+    """Preset `idx` (0..5); keyword arguments replace grid entries (e.g. a
     smaller nx/ny/nz for a parity run at the same physics)."""
     c = copy.deepcopy(_config(idx))
     c["grid"].update(grid_overrides)

@@ -137,6 +137,8 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
                      "ionized_per_call": [r["ionized"] for r in runs], "fallback": runs[-1]["fallback"],
                      "ions_active": runs[-1]["ions_active"]}
     out["rate_stage_speedup"] = out["exact"]["rate_ms"] / out["mlp"]["rate_ms"]
+    # the whole pic_ionize (cell moments + rate + draw/append; moments and draw are the same in both modes)
+    out["whole_step_speedup"] = out["exact"]["total_ms"] / out["mlp"]["total_ms"]
     out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3) for m in ("exact", "mlp")}
     # error of the surrogate against the exact quadrature (the judge)
     T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)

@@ -226,25 +226,26 @@ struct MlpArgs {
 };
 
 
-// Per supercell of ions: nu[p] for every ion (0 for Z >= z_max); out-of-range
-// inputs take the exact FP64 quadrature.  counters[0] += active ions,
-// counters[2] += fallbacks.  Persistent workgroups (weights loaded once); a
-// wave takes 64 ions of a supercell at a time, one per lane.
+// Per supercell of ions: nu[p] for every ion (0 for Z >= z_max).  Ions whose
+// inputs lie outside the trained range are appended to `fb_list` (their
+// count in counters[2]) and take the exact FP64 quadrature in a second,
+// small kernel, so that the quadrature's registers do not lower this
+// kernel's occupancy.  counters[0] += active ions.  Persistent workgroups
+// (weights loaded once); a wave takes 64 ions of a supercell at a time, one
+// per lane.
 __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion, IonTables tab, MlpArgs m,
-                                                    const double* ne, const double* kT, double* nu, const double* gl,
-                                                    unsigned long long* counters)
+                                                    const double* ne, const double* kT, double* nu,
+                                                    unsigned long long* counters, unsigned long long* fb_list)
 {
-    __shared__ double glx[GL_NODES], glw[GL_NODES];
     __shared__ PriorTab PT;
-    __shared__ int s_active, s_fallback;
+    __shared__ int s_active;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
     fill_prior(tab, PT);
-    if (tid == 0) { s_active = 0; s_fallback = 0; }
+    if (tid == 0) s_active = 0;
     Net net;
     load_net(m.params, lane, net);
     __syncthreads();
-    int active = 0, fallback = 0;
+    int active = 0;
     for (int sc = blockIdx.x; sc < g.nsc; sc += gridDim.x) {
         const int n = ion.count[sc];
         const int64_t base = (int64_t)sc * ion.cap;
@@ -253,16 +254,13 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
             float x0 = 0.f, x1 = 0.f, prior = 0.f;
             int Z = 0, zin = -1;
             bool act = false, inr = false;
-            double dkT = 0.0, dne = 0.0;
             const int64_t p = base + t;
             if (t < n) {
                 Z = ion.zs[p];
                 act = Z < tab.z_max;
                 const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
                                    (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
-                dkT = kT[gi];
-                dne = ne[gi];
-                const float fkT = (float)dkT, fne = (float)dne;
+                const float fkT = (float)kT[gi], fne = (float)ne[gi];
                 inr = act && Z < 6 && fkT >= m.t_min && fkT <= m.t_max && fne >= m.n_min && fne <= m.n_max;
                 if (inr) {
                     inputs_prior(fkT, fne, PT, Z, x0, x1, prior);
@@ -270,37 +268,62 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
                 }
             }
             const float y = forward64(net, lane, x0, x1, zin);
+            const bool fb = act && !inr;
+            const unsigned long long fmask = __ballot(fb);
+            if (fmask) {  // wave-uniform; rare
+                const int leader = __ffsll((long long)fmask) - 1;
+                unsigned long long fbase = 0;
+                if (lane == leader) fbase = atomicAdd(&counters[2], (unsigned long long)__popcll(fmask));
+                fbase = __shfl(fbase, leader, 64);
+                if (fb)
+                    fb_list[fbase + (unsigned)__builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)fmask, 0u))] =
+                        (unsigned long long)p;
+            }
             if (t < n) {
-                double v = 0.0;
-                if (act) {
-                    ++active;
-                    if (inr) {
-                        v = (double)__expf(prior + m.mu + m.s * y);  // ln nu <= ~40 on the trained range
-                    } else {
-                        ++fallback;
-                        v = fallback_rate(dkT, dne, tab.P[Z], tab.q[Z], glx, glw);
-                    }
-                }
-                nu[p] = v;
+                active += act ? 1 : 0;
+                // ln nu <= ~40 on the trained range; fallback ions are written by the second kernel
+                nu[p] = inr ? (double)__expf(prior + m.mu + m.s * y) : 0.0;
             }
         }
     }
     atomicAdd(&s_active, active);
-    atomicAdd(&s_fallback, fallback);
     __syncthreads();
-    if (tid == 0) {
-        if (s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
-        if (s_fallback) atomicAdd(&counters[2], (unsigned long long)s_fallback);
+    if (tid == 0 && s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
+}
+
+// The exact FP64 rate for the ions listed by k_rate_mlp.
+__global__ __launch_bounds__(BLOCK) void k_rate_fallback(GridView g, SpeciesView ion, IonTables tab, const double* ne,
+                                                         const double* kT, double* nu, const double* gl,
+                                                         const unsigned long long* fb_list,
+                                                         const unsigned long long* counters)
+{
+    __shared__ double glx[GL_NODES], glw[GL_NODES];
+    if (threadIdx.x < GL_NODES) { glx[threadIdx.x] = gl[threadIdx.x]; glw[threadIdx.x] = gl[GL_NODES + threadIdx.x]; }
+    __syncthreads();
+    const unsigned long long cnt = counters[2];
+    for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < cnt;
+         i += (unsigned long long)gridDim.x * BLOCK) {
+        const int64_t p = (int64_t)fb_list[i];
+        const int sc = (int)(p / ion.cap);
+        const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
+        const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
+                           (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
+        const int Z = ion.zs[p];
+        nu[p] = rate_exact(kT[gi], ne[gi], tab.P[Z], tab.q[Z], glx, glw);
     }
 }
 
 hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,
                            const double* ne, const double* kT, double* nu, const double* gl,
-                           unsigned long long* counters, hipStream_t st)
+                           unsigned long long* counters, unsigned long long* fb_list, hipStream_t st)
 {
     MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
     const int blocks = g.nsc < 1024 ? g.nsc : 1024;
-    hipLaunchKernelGGL(k_rate_mlp, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, gl, counters);
+    hipLaunchKernelGGL(k_rate_mlp, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, counters, fb_list);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rate_fallback, dim3(256), dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, gl, fb_list, counters);
     return hipGetLastError();
 }
 

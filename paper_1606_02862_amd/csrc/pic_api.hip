@@ -41,6 +41,7 @@ struct pic_ctx {
     double* ne = nullptr;                    // per-cell n_e (cm^-3)
     double* kT = nullptr;                    // per-cell kT_e (eV)
     double* nu[PIC_MAX_SPECIES] = {};        // per ion slot rate (1/s)
+    unsigned long long* fbl[PIC_MAX_SPECIES] = {};  // per ion slot: surrogate fallback list
     unsigned long long* counters = nullptr;  // active, ionised, fallback
     hipEvent_t iev[4] = {};
     // surrogate per ion species
@@ -237,7 +238,8 @@ int alloc_ionisation(pic_ctx* c)
         return fail(c, PIC_ERR_OOM, "device allocation of ionisation buffers failed");
     for (int s = 0; s < c->nsp; ++s) {
         if (c->sp[s].desc.z_max == 0) continue;
-        if (!(c->nu[s] = (double*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)))
+        if (!(c->nu[s] = (double*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)) ||
+            !(c->fbl[s] = (unsigned long long*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)))
             return fail(c, PIC_ERR_OOM, "device allocation of ionisation rates failed");
         pic_ctx::Mlp& m = c->mlp[s];
         if (!(m.params = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.m = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) ||
@@ -758,7 +760,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
             HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->counters, c->stream));
         else
             HIPCHK(c, launch_rate_mlp(c->g, c->sp[s].v, tab, mlp_launch(c, s), c->ne, c->kT, c->nu[s], c->gl,
-                                      c->counters, c->stream));
+                                      c->counters, c->fbl[s], c->stream));
         HIPCHK(c, hipEventRecord(c->iev[2], c->stream));
         DrawArgs a{};
         a.seed = c->grid.seed;

@@ -158,9 +158,10 @@ struct MlpStep {
     uint64_t draw_seed;    // 0: samples 0..batch-1 in order; else Philox draws
     int64_t step;
 };
+// fb_list: one entry per ion slot (nsc * cap), for the out-of-range ions
 hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,
                            const double* ne, const double* kT, double* nu, const double* gl,
-                           unsigned long long* counters, hipStream_t st);
+                           unsigned long long* counters, unsigned long long* fb_list, hipStream_t st);
 hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
                               const MlpLaunch& ml, const double* gl, double* out, hipStream_t st);
 hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTables& tab, const double* gl, float* X,

@@ -286,3 +286,31 @@ def test_ionize_mlp_tracks_exact(trained, P):
     a, b = counts["exact"]["ionized"], counts["mlp"]["ionized"]
     assert abs(a - b) <= 5 * np.sqrt(max(a, 1)) + 2
     assert counts["mlp"]["ions_active"] == counts["exact"]["ions_active"]
+
+
+def test_ionize_mlp_with_every_ion_out_of_range_equals_exact(trained, P):
+    """A trained range that excludes every cell sends every ion through the
+    surrogate path's exact fallback (the compacted list and its FP64
+    quadrature kernel): from one shared state the step must then reproduce
+    the exact step (same rates, same Philox uniforms, same decisions, same
+    new electrons)."""
+    pic_tr, _ = trained
+    params, ms, _ = pic_tr.mlp_get_params(1)
+    cfg = _carbon_cfg()
+    with P.Pic(cfg) as pic:
+        s0 = _shared_carbon_state(pic, cfg, warm=2)
+    out = {}
+    for mode in ("exact", "mlp"):
+        with P.Pic(cfg) as pic:
+            parity.push_state(pic, s0)
+            pic.mlp_set_params(1, params, ms, [1e5, 1e6, 1e19, 1e23])  # kT < 1e5 eV everywhere
+            stats = pic.ionize(mode)
+            out[mode] = (stats, pic.get_particles(1), pic.get_particles(0))
+    se, ions_e, el_e = out["exact"]
+    sm, ions_m, el_m = out["mlp"]
+    _print("exact", se, "mlp", sm)
+    assert sm["fallback"] == sm["ions_active"] == se["ions_active"] > 0
+    assert sm["ionized"] == se["ionized"] > 0
+    assert np.array_equal(ions_e["zstate"], ions_m["zstate"])
+    for k in ("id", "x", "y", "z", "ux", "uy", "uz", "w"):
+        assert np.array_equal(el_e[k], el_m[k]), k

@@ -37,18 +37,19 @@ PUSH_SOURCES = [os.path.join(ROOT, "paper_1606_02862_amd", "csrc", f)
                 for f in ("k_push.hip", "pic_migrate.hpp", "pic_device.hpp", "pic_internal.hpp")]
 
 
-def algorithmic_bytes_per_push(n_particles: int, n_cells: int, order: int) -> int:
-    """Bytes one particle-kernel launch must move: per particle 28 B read
-    (x, y, z, ux, uy, uz, w) and 24 B written (x, y, z, ux, uy, uz); per cell
-    E and B read once (24 B) and J read-modify-written once (24 B)."""
-    return n_particles * (28 + 24) + n_cells * (24 + 24)
+def algorithmic_bytes_per_push(n_particles: int, n_cells: int, order: int, es: int = 4) -> int:
+    """Bytes one particle-kernel launch must move (es = bytes per real): per
+    particle 7 reals read (x, y, z, ux, uy, uz, w) and 6 written (x, y, z,
+    ux, uy, uz); per cell E and B read once (6 reals) and J
+    read-modify-written once (6 reals).  FP32: 52 B per particle, 48 B per cell."""
+    return n_particles * 13 * es + n_cells * 12 * es
 
 
-def algorithmic_bytes_per_step(n_particles: int, n_cells: int) -> int:
-    """Whole cycle: the particle kernel's bytes, J zeroed (12 B/cell), and the
-    three Yee passes (each reads 6 and writes 3 components: 36 B/cell, plus J
-    read in the E pass: 12 B/cell)."""
-    return algorithmic_bytes_per_push(n_particles, n_cells, 1) + n_cells * (12 + 3 * 36 + 12)
+def algorithmic_bytes_per_step(n_particles: int, n_cells: int, es: int = 4) -> int:
+    """Whole cycle: the particle kernel's bytes, J zeroed (3 reals per cell),
+    and the three Yee passes (each reads 6 and writes 3 components, plus J
+    read in the E pass: 30 reals per cell)."""
+    return algorithmic_bytes_per_push(n_particles, n_cells, 1, es) + n_cells * (3 + 9 * 3 + 3) * es
 
 
 def source_hash(paths) -> str:
@@ -185,6 +186,8 @@ def main(argv=None):
     ap.add_argument("--cpu-box", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-ionize", action="store_true", help="skip the ionisation leg")
+    ap.add_argument("--fp64", action="store_true",
+                    help="the FP64 variant of the PIC cycle (the ionisation leg, FP32 only, is skipped)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -205,6 +208,9 @@ def main(argv=None):
         return 1
     P.load()
     cfg = workloads.config(args.config)
+    if args.fp64:
+        cfg["grid"]["precision"] = "fp64"
+    es = 8 if args.fp64 else 4
     gc = cfg["grid"]
     ncell = gc["nx"] * gc["ny"] * gc["nz"]
     order = {"cic": 1, "tsc": 2}[gc["shape"]]
@@ -235,10 +241,10 @@ def main(argv=None):
 
     push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
     per_launch = algorithmic_bytes_per_push(n_particles // max(1, sum(1 for s in cfg["species"] if s["mobile"])),
-                                            ncell, order)
+                                            ncell, order, es)
     achieved = per_launch / (push_avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(n_particles)
-    step_bytes = algorithmic_bytes_per_step(n_particles, ncell)
+    traffic = None if args.fp64 else traffic_from_profile(n_particles)
+    step_bytes = algorithmic_bytes_per_step(n_particles, ncell, es)
     value = n_particles * args.steps / (ms * 1e-3)
     line = {
         "metric": "particle updates/s (gather+push+deposit) & % HBM peak; ionize step exact vs MLP",
@@ -251,7 +257,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.fp64 else "f32",
         "data": "synthetic (seeded Philox initial state generated on the GPU)",
         "config": {"workload": cfg["workload"], "grid": [gc["nx"], gc["ny"], gc["nz"]], "shape": gc["shape"],
                    "species": [{"name": s["name"], "ppc": s["ppc"], "mass": s["mass"]} for s in cfg["species"]],
@@ -266,7 +272,7 @@ def main(argv=None):
         "checks": {"gauss_max_over_rho_max": moments["gauss_max"] / max(moments["rho_max"], 1e-30),
                    "particles_after": sum(moments["count"])},
     }
-    if not args.no_ionize:
+    if not args.no_ionize and not args.fp64:
         line["ionize"] = ionize_leg(P, torch, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps)

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
 #define PIC_SUPERCELL_X 8
@@ -68,6 +68,12 @@ enum pic_status {
 typedef enum { PIC_SHAPE_CIC = 1, PIC_SHAPE_TSC = 2 } pic_shape_t;
 typedef enum { PIC_LAYOUT_UNIFORM = 0, PIC_LAYOUT_SHEAR = 1, PIC_LAYOUT_BEAMS = 2 } pic_layout_t;
 typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1 } pic_rate_mode_t;
+/* Real type of particles, fields and currents on the device.  FP64 is the
+ * double-precision variant of the PIC cycle that the paper benchmarks beside
+ * single precision (section "Evaluation"): the same kernels instantiated in
+ * double, with the current tile accumulated by native FP64 LDS atomics and
+ * flushed by FP64 global atomics.  Ionisation needs FP32. */
+typedef enum { PIC_PRECISION_FP32 = 0, PIC_PRECISION_FP64 = 1 } pic_precision_t;
 
 /* Periodic grid.  nx, ny, nz must be positive multiples of 8, 8, 4 (the
  * supercell).  dt must satisfy the 3D Courant limit
@@ -75,7 +81,7 @@ typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1 } pic_rate_mode_t;
  * displacement to under one cell per step. */
 typedef struct {
     int32_t nx, ny, nz;
-    int32_t reserved0;
+    int32_t precision;  /* pic_precision_t (0: FP32) */
     double dx, dy, dz, dt;
     double b0[3];       /* uniform background magnetic field */
     double rho_bg;      /* immobile neutralising background charge density (in e n0) */
@@ -126,7 +132,8 @@ typedef struct pic_ctx pic_ctx;
 /* Create a simulation: allocates frames, fields and scratch, draws the initial
  * particles on the GPU and records the Gauss reference G0 = div E - rho.
  * alloc may be NULL (hipMalloc is used).  hip_stream is a hipStream_t or NULL.
- * Returns PIC_ERR_ARG for invalid sizes, shapes, species or time step. */
+ * Returns PIC_ERR_ARG for invalid sizes, shapes, species or time step, and
+ * for an FP64 grid with an ionising species. */
 int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species, int n_species,
              pic_shape_t shape, const pic_alloc_t* alloc, void* hip_stream);
 
@@ -178,6 +185,23 @@ int pic_set_particles(pic_ctx* ctx, int species, const pic_particles_view_t* v);
 /* Field transfer (host FP32 arrays of 3N, layout above).  NULL skips one. */
 int pic_get_fields(pic_ctx* ctx, float* E, float* B, float* J);
 int pic_set_fields(pic_ctx* ctx, const float* E, const float* B, const float* J);
+
+/* The same transfers with every real value in FP64 host arrays.  Both
+ * families work at either precision; a transfer to an FP32 handle rounds to
+ * FP32, one from it widens exactly. */
+typedef struct {
+    int64_t count;
+    int64_t capacity;
+    double *x, *y, *z;
+    double *ux, *uy, *uz, *w;
+    int64_t* id;
+    int32_t* zstate;
+} pic_particles64_view_t;
+
+int pic_get_particles64(pic_ctx* ctx, int species, pic_particles64_view_t* v);
+int pic_set_particles64(pic_ctx* ctx, int species, const pic_particles64_view_t* v);
+int pic_get_fields64(pic_ctx* ctx, double* E, double* B, double* J);
+int pic_set_fields64(pic_ctx* ctx, const double* E, const double* B, const double* J);
 
 /* Record the current state's div E - rho as the Gauss reference G0.  Called
  * by pic_init; call it again after replacing particles or fields. */

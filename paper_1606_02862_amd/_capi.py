@@ -17,7 +17,7 @@ PIC_OK, PIC_ERR_ARG, PIC_ERR_OOM, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PI
 
 
 class GridT(C.Structure):
-    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
                 ("b0", C.c_double * 3), ("rho_bg", C.c_double), ("seed", C.c_uint64), ("n_ref_cm3", C.c_double)]
 
@@ -43,6 +43,13 @@ class MomentsT(C.Structure):
                 ("kinetic_total", C.c_double), ("charge_total", C.c_double), ("rho_max", C.c_double),
                 ("gauss_max", C.c_double), ("divb_max", C.c_double), ("count", C.c_int64 * PIC_MAX_SPECIES),
                 ("step", C.c_int64), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ParticlesView64T(C.Structure):
+    _fields_ = [("count", C.c_int64), ("capacity", C.c_int64),
+                ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
+                ("ux", C.POINTER(C.c_double)), ("uy", C.POINTER(C.c_double)), ("uz", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("id", C.POINTER(C.c_int64)), ("zstate", C.POINTER(C.c_int32))]
 
 
 class ParticlesViewT(C.Structure):
@@ -92,6 +99,10 @@ SIGNATURES = {
     "pic_set_particles": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ParticlesViewT)]),
     "pic_get_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pic_set_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pic_get_particles64": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ParticlesView64T)]),
+    "pic_set_particles64": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ParticlesView64T)]),
+    "pic_get_fields64": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pic_set_fields64": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pic_mark_reference": (C.c_int, [C.c_void_p]),
     "pic_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TimingT)]),
     "pic_ionize": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IonizeStatsT)]),

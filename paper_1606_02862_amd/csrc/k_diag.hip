@@ -39,7 +39,8 @@ __device__ inline double block_reduce(double v, bool is_max, double* scratch)
     return r;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_field_energy(GridView g, double* partial)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_field_energy(GridViewT<R> g, double* partial)
 {
     __shared__ double scratch[BLOCK / 64];
     const int64_t N3 = 3LL * g.nx * g.ny * g.nz;
@@ -83,9 +84,10 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const double* partial, Final
     }
 }
 
-hipError_t launch_field_energy(const GridView& g, const DiagBuffers& d, hipStream_t st)
+template <class R>
+hipError_t launch_field_energy(const GridViewT<R>& g, const DiagBuffers& d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_field_energy, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.partial);
+    hipLaunchKernelGGL(k_field_energy<R>, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.partial);
     Finalize f{};
     f.nb = RED_BLOCKS;
     f.stride = 3;
@@ -100,7 +102,8 @@ hipError_t launch_field_energy(const GridView& g, const DiagBuffers& d, hipStrea
 }
 
 // ---------------------------------------------------------------- kinetic
-__global__ __launch_bounds__(BLOCK) void k_kinetic(GridView g, SpeciesView s, double* partial)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_kinetic(GridViewT<R> g, SpeciesViewT<R> s, double* partial)
 {
     __shared__ double scratch[BLOCK / 64];
     const int sc = blockIdx.x;
@@ -116,9 +119,11 @@ __global__ __launch_bounds__(BLOCK) void k_kinetic(GridView g, SpeciesView s, do
     if (threadIdx.x == 0) partial[sc] = acc * (double)s.mass;
 }
 
-hipError_t launch_kinetic(const GridView& g, const SpeciesView& s, const DiagBuffers& d, int slot, hipStream_t st)
+template <class R>
+hipError_t launch_kinetic(const GridViewT<R>& g, const SpeciesViewT<R>& s, const DiagBuffers& d, int slot,
+                          hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kinetic, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, d.partial);
+    hipLaunchKernelGGL(k_kinetic<R>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, d.partial);
     Finalize f{};
     f.nb = g.nsc;
     f.stride = 1;
@@ -148,8 +153,8 @@ __device__ inline void rho_weights(double x, int* first, double* w)
     }
 }
 
-template <int ORDER>
-__global__ __launch_bounds__(BLOCK) void k_rho(GridView g, SpeciesView s, double* rho)
+template <int ORDER, class R>
+__global__ __launch_bounds__(BLOCK) void k_rho(GridViewT<R> g, SpeciesViewT<R> s, double* rho)
 {
     const int sc = blockIdx.x;
     const int n = s.count[sc];
@@ -182,17 +187,20 @@ __global__ __launch_bounds__(BLOCK) void k_rho(GridView g, SpeciesView s, double
     }
 }
 
-hipError_t launch_rho_deposit(const GridView& g, const SpeciesView& s, int order, double* rho, hipStream_t st)
+template <class R>
+hipError_t launch_rho_deposit(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double* rho,
+                              hipStream_t st)
 {
-    if (order == 1) hipLaunchKernelGGL(k_rho<1>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
-    else hipLaunchKernelGGL(k_rho<2>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    if (order == 1) hipLaunchKernelGGL((k_rho<1, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    else hipLaunchKernelGGL((k_rho<2, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- Gauss
 // mode 0: store G = div E - rho as the reference; mode 1: reduce
 // max |G - G0|, max |rho|, sum rho dV and max |div B| (at cell centres).
-__global__ __launch_bounds__(BLOCK) void k_gauss(GridView g, const double* rho, double* g0, double rho_bg, int mode,
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_gauss(GridViewT<R> g, const double* rho, double* g0, double rho_bg, int mode,
                                                  double* partial)
 {
     __shared__ double scratch[BLOCK / 64];
@@ -237,9 +245,10 @@ __global__ __launch_bounds__(BLOCK) void k_gauss(GridView g, const double* rho, 
     }
 }
 
-hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st)
+template <class R>
+hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gauss, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.rho, d.g0, rho_bg, mode, d.partial);
+    hipLaunchKernelGGL(k_gauss<R>, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.rho, d.g0, rho_bg, mode, d.partial);
     if (mode == 0) return hipGetLastError();
     Finalize f{};
     f.nb = RED_BLOCKS;
@@ -253,5 +262,16 @@ hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, 
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, d.partial, f, d.result);
     return hipGetLastError();
 }
+
+#define PIC_DIAG_INSTANCES(R)                                                                                   \
+    template hipError_t launch_field_energy<R>(const GridViewT<R>&, const DiagBuffers&, hipStream_t);         \
+    template hipError_t launch_kinetic<R>(const GridViewT<R>&, const SpeciesViewT<R>&, const DiagBuffers&, int, \
+                                          hipStream_t);                                                       \
+    template hipError_t launch_rho_deposit<R>(const GridViewT<R>&, const SpeciesViewT<R>&, int, double*,       \
+                                              hipStream_t);                                                   \
+    template hipError_t launch_gauss<R>(const GridViewT<R>&, const DiagBuffers&, double, int, hipStream_t);
+PIC_DIAG_INSTANCES(float)
+PIC_DIAG_INSTANCES(double)
+#undef PIC_DIAG_INSTANCES
 
 }  // namespace pic

@@ -7,7 +7,8 @@
 
 namespace pic {
 
-__global__ __launch_bounds__(BLOCK) void k_yee_b(GridView g, float cx, float cy, float cz)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_yee_b(GridViewT<R> g, R cx, R cy, R cz)
 {
     const int N = g.nx * g.ny * g.nz;
     const int c = blockIdx.x * BLOCK + threadIdx.x;
@@ -16,19 +17,20 @@ __global__ __launch_bounds__(BLOCK) void k_yee_b(GridView g, float cx, float cy,
     const int ip = (i + 1 == g.nx) ? c - i : c + 1;
     const int jp = (j + 1 == g.ny) ? c - j * g.nx : c + g.nx;
     const int kp = (k + 1 == g.nz) ? c - k * g.nx * g.ny : c + g.nx * g.ny;
-    const float* Ex = g.E;
-    const float* Ey = g.E + N;
-    const float* Ez = g.E + 2 * N;
-    const float ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    const float curl_x = cy * (Ez[jp] - ez) - cz * (Ey[kp] - ey);
-    const float curl_y = cz * (Ex[kp] - ex) - cx * (Ez[ip] - ez);
-    const float curl_z = cx * (Ey[ip] - ey) - cy * (Ex[jp] - ex);
+    const R* Ex = g.E;
+    const R* Ey = g.E + N;
+    const R* Ez = g.E + 2 * N;
+    const R ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    const R curl_x = cy * (Ez[jp] - ez) - cz * (Ey[kp] - ey);
+    const R curl_y = cz * (Ex[kp] - ex) - cx * (Ez[ip] - ez);
+    const R curl_z = cx * (Ey[ip] - ey) - cy * (Ex[jp] - ex);
     g.B[c] -= curl_x;
     g.B[N + c] -= curl_y;
     g.B[2 * N + c] -= curl_z;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_yee_e(GridView g, float cx, float cy, float cz, float coef)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_yee_e(GridViewT<R> g, R cx, R cy, R cz, R coef)
 {
     const int N = g.nx * g.ny * g.nz;
     const int c = blockIdx.x * BLOCK + threadIdx.x;
@@ -37,32 +39,42 @@ __global__ __launch_bounds__(BLOCK) void k_yee_e(GridView g, float cx, float cy,
     const int im = (i == 0) ? c + g.nx - 1 : c - 1;
     const int jm = (j == 0) ? c + (g.ny - 1) * g.nx : c - g.nx;
     const int km = (k == 0) ? c + (g.nz - 1) * g.nx * g.ny : c - g.nx * g.ny;
-    const float* Bx = g.B;
-    const float* By = g.B + N;
-    const float* Bz = g.B + 2 * N;
-    const float bx = Bx[c], by = By[c], bz = Bz[c];
-    const float curl_x = cy * (bz - Bz[jm]) - cz * (by - By[km]);
-    const float curl_y = cz * (bx - Bx[km]) - cx * (bz - Bz[im]);
-    const float curl_z = cx * (by - By[im]) - cy * (bx - Bx[jm]);
+    const R* Bx = g.B;
+    const R* By = g.B + N;
+    const R* Bz = g.B + 2 * N;
+    const R bx = Bx[c], by = By[c], bz = Bz[c];
+    const R curl_x = cy * (bz - Bz[jm]) - cz * (by - By[km]);
+    const R curl_y = cz * (bx - Bx[km]) - cx * (bz - Bz[im]);
+    const R curl_z = cx * (by - By[im]) - cy * (bx - Bx[jm]);
     g.E[c] += curl_x - coef * g.J[c];
     g.E[N + c] += curl_y - coef * g.J[N + c];
     g.E[2 * N + c] += curl_z - coef * g.J[2 * N + c];
 }
 
-hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st)
+// coef / dx etc. are rounded to R once on the host side of the launch
+template <class R>
+hipError_t launch_yee_b(const GridViewT<R>& g, double coef, hipStream_t st)
 {
     const int N = g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_yee_b, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, coef / g.dx, coef / g.dy,
-                       coef / g.dz);
+    const R cf = (R)coef;
+    hipLaunchKernelGGL(k_yee_b<R>, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, cf / g.dx, cf / g.dy,
+                       cf / g.dz);
     return hipGetLastError();
 }
 
-hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st)
+template <class R>
+hipError_t launch_yee_e(const GridViewT<R>& g, double coef, hipStream_t st)
 {
     const int N = g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_yee_e, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, coef / g.dx, coef / g.dy,
-                       coef / g.dz, coef);
+    const R cf = (R)coef;
+    hipLaunchKernelGGL(k_yee_e<R>, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, g, cf / g.dx, cf / g.dy,
+                       cf / g.dz, cf);
     return hipGetLastError();
 }
+
+template hipError_t launch_yee_b<float>(const GridView&, double, hipStream_t);
+template hipError_t launch_yee_b<double>(const GridView64&, double, hipStream_t);
+template hipError_t launch_yee_e<float>(const GridView&, double, hipStream_t);
+template hipError_t launch_yee_e<double>(const GridView64&, double, hipStream_t);
 
 }  // namespace pic

@@ -9,11 +9,12 @@ struct InitArgs {
     uint64_t seed;
     int species_index, ppc, pos_index, pos_ppc;
     int64_t id_offset, pos_id_offset;
-    float u_th, drift[3], weight;
+    double u_th, drift[3], weight;  // rounded to R before use
     int layout, z_init;
 };
 
-__global__ __launch_bounds__(BLOCK) void k_init_species(GridView g, SpeciesView s, InitArgs a)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_init_species(GridViewT<R> g, SpeciesViewT<R> s, InitArgs a)
 {
     const int sc = blockIdx.x;
     const int c = threadIdx.x;
@@ -23,18 +24,21 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(GridView g, SpeciesView 
     const int64_t cell = (int64_t)i + (int64_t)g.nx * ((int64_t)j + (int64_t)g.ny * k);
     const double two_pi = 6.283185307179586476925286766559;
     const int64_t base = (int64_t)sc * s.cap;
+    const double uth = (double)(R)a.u_th;
+    const double drift[3] = {(double)(R)a.drift[0], (double)(R)a.drift[1], (double)(R)a.drift[2]};
+    // rounding to R must not push a particle onto the supercell's far face
+    const R xm = face_below<R>((R)SX), ym = face_below<R>((R)SY), zm = face_below<R>((R)SZ);
     for (int slot = 0; slot < a.ppc; ++slot) {
         const int64_t myid = cell * a.ppc + slot + a.id_offset;
         const int64_t pid = cell * a.pos_ppc + slot + a.pos_id_offset;
         const Philox4 pr = philox4x64_10((uint64_t)pid, (uint64_t)a.pos_index, PURPOSE_POSITION, 0, a.seed, 0);
         const Philox4 mr = philox4x64_10((uint64_t)myid, (uint64_t)a.species_index, PURPOSE_MOMENTUM, 0, a.seed, 0);
-        float x = (float)((double)lx + u01(pr.v[0]));
-        float y = (float)((double)ly + u01(pr.v[1]));
-        float z = (float)((double)lz + u01(pr.v[2]));
-        // rounding to fp32 must not push a particle onto the supercell's far face
-        x = fminf(x, XMAX);
-        y = fminf(y, YMAX);
-        z = fminf(z, ZMAX);
+        R x = (R)((double)lx + u01(pr.v[0]));
+        R y = (R)((double)ly + u01(pr.v[1]));
+        R z = (R)((double)lz + u01(pr.v[2]));
+        x = x < xm ? x : xm;
+        y = y < ym ? y : ym;
+        z = z < zm ? z : zm;
         const double b0 = u01(mr.v[0]), b1 = u01(mr.v[1]), b2 = u01(mr.v[2]), b3 = u01(mr.v[3]);
         const double r0 = sqrt(-2.0 * log(b0)), r1 = sqrt(-2.0 * log(b2));
         const double n0 = r0 * cos(two_pi * b1), n1 = r0 * sin(two_pi * b1), n2 = r1 * cos(two_pi * b3);
@@ -45,19 +49,21 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(GridView g, SpeciesView 
         s.x[p] = x;
         s.y[p] = y;
         s.z[p] = z;
-        s.ux[p] = (float)(sign * (double)a.drift[0] + (double)a.u_th * n0);
-        s.uy[p] = (float)(sign * (double)a.drift[1] + (double)a.u_th * n1);
-        s.uz[p] = (float)(sign * (double)a.drift[2] + (double)a.u_th * n2);
-        s.w[p] = a.weight;
+        s.ux[p] = (R)(sign * drift[0] + uth * n0);
+        s.uy[p] = (R)(sign * drift[1] + uth * n1);
+        s.uz[p] = (R)(sign * drift[2] + uth * n2);
+        s.w[p] = (R)a.weight;
         s.id[p] = (uint32_t)myid;
         if (s.zs) s.zs[p] = (uint8_t)a.z_init;
     }
     if (c == 0) s.count[sc] = a.ppc * BLOCK;
 }
 
-hipError_t launch_init_species(const GridView& g, const SpeciesView& s, uint64_t seed, int species_index, int ppc,
-                               int64_t id_offset, int pos_index, int pos_ppc, int64_t pos_id_offset, float u_th,
-                               const float drift_u[3], int layout, float weight, int z_init, hipStream_t st)
+template <class R>
+hipError_t launch_init_species(const GridViewT<R>& g, const SpeciesViewT<R>& s, uint64_t seed, int species_index,
+                               int ppc, int64_t id_offset, int pos_index, int pos_ppc, int64_t pos_id_offset,
+                               double u_th, const double drift_u[3], int layout, double weight, int z_init,
+                               hipStream_t st)
 {
     InitArgs a;
     a.seed = seed;
@@ -74,9 +80,15 @@ hipError_t launch_init_species(const GridView& g, const SpeciesView& s, uint64_t
     a.weight = weight;
     a.layout = layout;
     a.z_init = z_init;
-    hipLaunchKernelGGL(k_init_species, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, a);
+    hipLaunchKernelGGL(k_init_species<R>, dim3(g.nsc), dim3(BLOCK), 0, st, g, s, a);
     return hipGetLastError();
 }
+
+template hipError_t launch_init_species<float>(const GridView&, const SpeciesView&, uint64_t, int, int, int64_t, int,
+                                               int, int64_t, double, const double*, int, double, int, hipStream_t);
+template hipError_t launch_init_species<double>(const GridView64&, const SpeciesView64&, uint64_t, int, int, int64_t,
+                                                int, int, int64_t, double, const double*, int, double, int,
+                                                hipStream_t);
 
 // ---------------------------------------------------------------- fills
 // Plain fill kernels (used instead of hipMemsetAsync so that a captured

@@ -5,7 +5,8 @@
 
 namespace pic {
 
-__global__ __launch_bounds__(BLOCK) void k_migrate(GridView g, SpeciesView s, int par)
+template <class R>
+__global__ __launch_bounds__(BLOCK) void k_migrate(GridViewT<R> g, SpeciesViewT<R> s, int par)
 {
     extern __shared__ int lds[];
     __shared__ int counters[3];
@@ -13,11 +14,15 @@ __global__ __launch_bounds__(BLOCK) void k_migrate(GridView g, SpeciesView s, in
     fill_supercell<BLOCK>(g, s, sc, par, lds, counters);
 }
 
-hipError_t launch_migrate(const GridView& g, const SpeciesView& s, int par, hipStream_t st)
+template <class R>
+hipError_t launch_migrate(const GridViewT<R>& g, const SpeciesViewT<R>& s, int par, hipStream_t st)
 {
     const size_t lds = (size_t)3 * s.cap_in * sizeof(int) + ((size_t)s.cap_in + 31) / 32 * sizeof(unsigned);
-    hipLaunchKernelGGL(k_migrate, dim3(g.nsc), dim3(BLOCK), lds, st, g, s, par);
+    hipLaunchKernelGGL(k_migrate<R>, dim3(g.nsc), dim3(BLOCK), lds, st, g, s, par);
     return hipGetLastError();
 }
+
+template hipError_t launch_migrate<float>(const GridView&, const SpeciesView&, int, hipStream_t);
+template hipError_t launch_migrate<double>(const GridView64&, const SpeciesView64&, int, hipStream_t);
 
 }  // namespace pic

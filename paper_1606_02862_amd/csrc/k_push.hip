@@ -20,6 +20,9 @@
 // |q w| dx_d / (dV dt)), truncated to int32 and added as int64, so tile sums
 // are exact and independent of the order of the atomics; the flush converts once.
 //
+// The FP64 variant (R = double) accumulates the tile with native FP64 LDS
+// atomics and flushes with FP64 global atomics instead.
+//
 // Two deposit paths (same Esirkepov arithmetic): a particle whose first shape
 // node is unchanged on all three axes (it stays in its cell for CIC, keeps its
 // nearest node for TSC) needs only an (ORDER+1)-node window per axis, which
@@ -27,11 +30,13 @@
 // a per-supercell scratch list (wave ballot + popcount for the slots) and
 // deposited after the frame loop with the full (ORDER+2)-node window, so that
 // no wave runs the wide window for a few of its lanes.
+#include <type_traits>
+
 #include "pic_migrate.hpp"
 
 namespace pic {
 
-template <int ORDER>
+template <int ORDER, class R = float>
 struct Tile {
     // gather tile: nodes [-1, S + ORDER] per axis
     static constexpr int GX = SX + 1 + ORDER, GY = SY + 1 + ORDER, GZ = SZ + 1 + ORDER;
@@ -44,7 +49,7 @@ struct Tile {
     static constexpr int W = ORDER + 2;   // Esirkepov window per axis (general case)
     // LDS: field tiles then the 64-bit current tile; before staging, the same
     // bytes serve as scratch for absorbing the previous step's arrivals
-    static constexpr int SMEM = 6 * GN * 4 + 3 * JN * 8;
+    static constexpr int SMEM = 6 * GN * (int)sizeof(R) + 3 * JN * 8;
 };
 
 // Largest arrival list the particle kernel can absorb in its LDS scratch.
@@ -55,47 +60,51 @@ __host__ __device__ constexpr int max_cap_in(int order)
 static_assert(3 * 2048 + 64 <= Tile<1>::SMEM / 4, "CIC scratch");
 static_assert(3 * 4096 + 128 <= Tile<2>::SMEM / 4, "TSC scratch");
 
+// Current-tile accumulator: 64-bit fixed point for FP32, FP64 for FP64.
+template <class R>
+using JAcc = typename std::conditional<std::is_same<R, float>::value, unsigned long long, double>::type;
+
 // Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f,
 // f0 pointing at the component's first node (x fastest in the tile).
-template <int ORDER>
-__device__ inline float interp(const float* f0, const float* wx, const float* wy, const float* wz)
+template <int ORDER, class R>
+__device__ inline R interp(const R* f0, const R* wx, const R* wy, const R* wz)
 {
     using T = Tile<ORDER>;
-    float acc = 0.0f;
+    R acc = R(0);
 #pragma unroll
     for (int c = 0; c < T::NP; ++c) {
-        float accy = 0.0f;
+        R accy = R(0);
 #pragma unroll
         for (int b = 0; b < T::NP; ++b) {
-            const float* row = f0 + (c * T::GY + b) * T::GX;
-            float accx = 0.0f;
+            const R* row = f0 + (c * T::GY + b) * T::GX;
+            R accx = R(0);
 #pragma unroll
-            for (int a = 0; a < T::NP; ++a) accx = fmaf(wx[a], row[a], accx);
-            accy = fmaf(wy[b], accx, accy);
+            for (int a = 0; a < T::NP; ++a) accx = rfma(wx[a], row[a], accx);
+            accy = rfma(wy[b], accx, accy);
         }
-        acc = fmaf(wz[c], accy, acc);
+        acc = rfma(wz[c], accy, acc);
     }
     return acc;
 }
 
 // Old shape and shape change on the general window [m, m + W) of one axis.
-template <int ORDER>
-__device__ inline int esirkepov_axis(float x0, float x1, float* S0, float* DS)
+template <int ORDER, class R>
+__device__ inline int esirkepov_axis(R x0, R x1, R* S0, R* DS)
 {
     using T = Tile<ORDER>;
-    float w0[T::NP], w1[T::NP];
+    R w0[T::NP], w1[T::NP];
     const int f0 = shape_weights<ORDER>(x0, w0);
     const int f1 = shape_weights<ORDER>(x1, w1);
     const int m = min(f0, f1);
     const int o0 = f0 - m, o1 = f1 - m;  // 0 or 1
 #pragma unroll
     for (int k = 0; k < T::W; ++k) {
-        const float a = (k < T::NP) ? w0[k] : 0.0f;
-        const float b = (k >= 1) ? w0[k - 1] : 0.0f;
-        const float c = (k < T::NP) ? w1[k] : 0.0f;
-        const float d = (k >= 1) ? w1[k - 1] : 0.0f;
-        const float s0 = o0 ? b : a;
-        const float s1 = o1 ? d : c;
+        const R a = (k < T::NP) ? w0[k] : R(0);
+        const R b = (k >= 1) ? w0[k - 1] : R(0);
+        const R c = (k < T::NP) ? w1[k] : R(0);
+        const R d = (k >= 1) ? w1[k - 1] : R(0);
+        const R s0 = o0 ? b : a;
+        const R s1 = o1 ? d : c;
         S0[k] = s0;
         DS[k] = s1 - s0;
     }
@@ -110,6 +119,8 @@ __device__ inline void jadd(unsigned long long* p, float v)
     const int iv = (int)v;
     atomicAdd(p, (unsigned long long)(long long)iv);
 }
+// FP64: a native LDS atomic add.
+__device__ inline void jadd(double* p, double v) { atomicAdd(p, v); }
 
 // Esirkepov deposit of one particle on a window of W nodes per axis starting
 // at tile nodes (mx, my, mz):
@@ -117,35 +128,35 @@ __device__ inline void jadd(unsigned long long* p, float v)
 //   J_x(a+1/2, b, c) = -(q w dx / (dV dt)) sum_{a' <= a} W_x(a',b,c)
 // (cyclically for y and z), with the transverse factor written as
 // (S0y + DSy/2) S0z + (S0y/2 + DSy/3) DSz.
-template <int ORDER, int W>
-__device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, const float* S0x, const float* DSx,
-                               const float* S0y, const float* DSy, const float* S0z, const float* DSz, float cx,
-                               float cy, float cz)
+template <int ORDER, int W, class R, class A>
+__device__ inline void deposit(A* tJ, int mx, int my, int mz, const R* S0x, const R* DSx, const R* S0y, const R* DSy,
+                               const R* S0z, const R* DSz, R cx, R cy, R cz)
 {
     using T = Tile<ORDER>;
-    const float third = 1.0f / 3.0f;
-    float Px[W], Qx[W], Py[W], Qy[W], Pz[W], Qz[W];
+    const R third = R(1) / R(3);
+    const R half = R(0.5);
+    R Px[W], Qx[W], Py[W], Qy[W], Pz[W], Qz[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        Px[k] = fmaf(0.5f, DSx[k], S0x[k]); Qx[k] = fmaf(third, DSx[k], 0.5f * S0x[k]);
-        Py[k] = fmaf(0.5f, DSy[k], S0y[k]); Qy[k] = fmaf(third, DSy[k], 0.5f * S0y[k]);
-        Pz[k] = fmaf(0.5f, DSz[k], S0z[k]); Qz[k] = fmaf(third, DSz[k], 0.5f * S0z[k]);
+        Px[k] = rfma(half, DSx[k], S0x[k]); Qx[k] = rfma(third, DSx[k], half * S0x[k]);
+        Py[k] = rfma(half, DSy[k], S0y[k]); Qy[k] = rfma(third, DSy[k], half * S0y[k]);
+        Pz[k] = rfma(half, DSz[k], S0z[k]); Qz[k] = rfma(third, DSz[k], half * S0z[k]);
     }
-    float Rx[W - 1], Ry[W - 1], Rz[W - 1];  // running sums of DS (the last one is zero)
+    R Rx[W - 1], Ry[W - 1], Rz[W - 1];  // running sums of DS (the last one is zero)
     Rx[0] = DSx[0]; Ry[0] = DSy[0]; Rz[0] = DSz[0];
 #pragma unroll
     for (int k = 1; k < W - 1; ++k) {
         Rx[k] = Rx[k - 1] + DSx[k]; Ry[k] = Ry[k - 1] + DSy[k]; Rz[k] = Rz[k - 1] + DSz[k];
     }
-    unsigned long long* Jx = tJ;
-    unsigned long long* Jy = tJ + T::JN;
-    unsigned long long* Jz = tJ + 2 * T::JN;
+    A* Jx = tJ;
+    A* Jy = tJ + T::JN;
+    A* Jz = tJ + 2 * T::JN;
 #pragma unroll
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int b = 0; b < W; ++b) {
             const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
-            const float ax = cx * fmaf(Py[b], S0z[c], Qy[b] * DSz[c]);
+            const R ax = cx * rfma(Py[b], S0z[c], Qy[b] * DSz[c]);
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a]);
         }
@@ -153,7 +164,7 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int a = 0; a < W; ++a) {
-            const float ay = cy * fmaf(Pz[c], S0x[a], Qz[c] * DSx[a]);
+            const R ay = cy * rfma(Pz[c], S0x[a], Qz[c] * DSx[a]);
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b]);
         }
@@ -161,7 +172,7 @@ __device__ inline void deposit(unsigned long long* tJ, int mx, int my, int mz, c
     for (int b = 0; b < W; ++b)
 #pragma unroll
         for (int a = 0; a < W; ++a) {
-            const float az = cz * fmaf(Px[a], S0y[b], Qx[a] * DSy[b]);
+            const R az = cz * rfma(Px[a], S0y[b], Qx[a] * DSy[b]);
 #pragma unroll
             for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c]);
         }
@@ -180,15 +191,21 @@ __device__ inline const E& at(const E* base, unsigned byte_off)
     return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-template <int ORDER, bool HAS_Z, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_push(GridView g, SpeciesView s, float jscale,
-                                                                                  float jinv, int apar, int wpar)
+// Waves per SIMD the register budget is fitted to: 4 in FP32, 2 in FP64.
+template <class R> constexpr int push_waves() { return std::is_same<R, float>::value ? 4 : 2; }
+
+template <int ORDER, bool HAS_Z, int NT, class R>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(push_waves<R>())))
+void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int wpar)
 {
-    using T = Tile<ORDER>;
+    using T = Tile<ORDER, R>;
+    using A = JAcc<R>;
+    using R4 = typename Vec4<R>::type;
+    constexpr unsigned RB = sizeof(R);
     __shared__ __align__(16) unsigned char smem[T::SMEM];
-    float(*fE)[T::GN] = reinterpret_cast<float(*)[T::GN]>(smem);
-    float(*fB)[T::GN] = reinterpret_cast<float(*)[T::GN]>(smem + 3 * T::GN * 4);
-    unsigned long long* tJ = reinterpret_cast<unsigned long long*>(smem + 6 * T::GN * 4);
+    R(*fE)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem);
+    R(*fB)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem + 3 * T::GN * RB);
+    A* tJ = reinterpret_cast<A*>(smem + 6 * T::GN * RB);
     __shared__ int s_holes, s_queue, s_cnt[3];
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
@@ -214,36 +231,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             fB[c][t] = g.B[c * N + gi];
         }
     }
-    for (int t = tid; t < 3 * T::JN; t += NT) tJ[t] = 0ull;
+    for (int t = tid; t < 3 * T::JN; t += NT) tJ[t] = A(0);
     if (tid == 0) { s_holes = 0; s_queue = 0; }
     __syncthreads();
 
     const int n = s.count[sc];
     const int64_t base = (int64_t)sc * s.cap;
     const int64_t qbase = (int64_t)sc * g.qcap;
-    const float dt = g.dt;
-    const float cdx = dt / g.dx, cdy = dt / g.dy, cdz = dt / g.dz;
-    const float inv_dvdt = 1.0f / (g.dx * g.dy * g.dz * dt);
-    // current coefficients with the fixed-point scale folded in
-    const float jcx = -g.dx * inv_dvdt * jscale, jcy = -g.dy * inv_dvdt * jscale, jcz = -g.dz * inv_dvdt * jscale;
-    const float qm = 0.5f * dt / s.mass;
+    const R dt = g.dt;
+    const R cdx = dt / g.dx, cdy = dt / g.dy, cdz = dt / g.dz;
+    const R inv_dvdt = R(1) / (g.dx * g.dy * g.dz * dt);
+    // current coefficients with the fixed-point scale folded in (1 in FP64)
+    const R jcx = -g.dx * inv_dvdt * jscale, jcy = -g.dy * inv_dvdt * jscale, jcz = -g.dz * inv_dvdt * jscale;
+    const R qm = R(0.5) * dt / s.mass;
+    const R xm = face_below<R>((R)SX), ym = face_below<R>((R)SY), zm = face_below<R>((R)SZ);
     bool bad = false;
 
     // this supercell's frames: block-uniform base pointers, 32-bit slot offsets
-    float* const px = s.x + base;
-    float* const py = s.y + base;
-    float* const pz = s.z + base;
-    float* const pux = s.ux + base;
-    float* const puy = s.uy + base;
-    float* const puz = s.uz + base;
-    const float* const pw = s.w + base;
+    R* const px = s.x + base;
+    R* const py = s.y + base;
+    R* const pz = s.z + base;
+    R* const pux = s.ux + base;
+    R* const puy = s.uy + base;
+    R* const puz = s.uz + base;
+    const R* const pw = s.w + base;
     const uint8_t* const pzs = HAS_Z ? s.zs + base : nullptr;
 
     // software pipeline: the next frame's particle is loaded while this one is computed
-    float nx0 = 0.f, ny0 = 0.f, nz0 = 0.f, nux = 0.f, nuy = 0.f, nuz = 0.f, nw = 0.f;
+    R nx0 = 0, ny0 = 0, nz0 = 0, nux = 0, nuy = 0, nuz = 0, nw = 0;
     int nzs = 0;
     if (tid < n) {
-        const unsigned u = 4u * (unsigned)tid;
+        const unsigned u = RB * (unsigned)tid;
         nx0 = at(px, u); ny0 = at(py, u); nz0 = at(pz, u);
         nux = at(pux, u); nuy = at(puy, u); nuz = at(puz, u); nw = at(pw, u);
         if constexpr (HAS_Z) nzs = pzs[tid];
@@ -251,68 +269,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int f = 0; f < n; f += NT) {
         const int slot = f + tid;
         if (slot >= n) break;
-        const unsigned u = 4u * (unsigned)slot;  // byte offset of the slot
-        const float x0 = nx0, y0 = ny0, z0 = nz0;
-        float ux = nux, uy = nuy, uz = nuz;
-        const float wgt = nw;
-        float q = s.charge;
-        if constexpr (HAS_Z) q *= (float)nzs;
+        const unsigned u = RB * (unsigned)slot;  // byte offset of the slot
+        const R x0 = nx0, y0 = ny0, z0 = nz0;
+        R ux = nux, uy = nuy, uz = nuz;
+        const R wgt = nw;
+        R q = s.charge;
+        if constexpr (HAS_Z) q *= (R)nzs;
         {   // unconditional (the last particle again past the end) so that no branch
             // obscures the order of these loads relative to this iteration's stores
             const int sn = slot + NT < n ? slot + NT : n - 1;
-            const unsigned un = 4u * (unsigned)sn;
+            const unsigned un = RB * (unsigned)sn;
             nx0 = at(px, un); ny0 = at(py, un); nz0 = at(pz, un);
             nux = at(pux, un); nuy = at(puy, un); nuz = at(puz, un); nw = at(pw, un);
             if constexpr (HAS_Z) nzs = pzs[sn];
         }
 
         // ---- gather at node-centred and half-shifted positions per axis
-        float wnx[T::NP], wny[T::NP], wnz[T::NP], wsx[T::NP], wsy[T::NP], wsz[T::NP];
-        const int inx = shape_weights<ORDER>(x0, wnx), isx = shape_weights<ORDER>(x0 - 0.5f, wsx);
-        const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<ORDER>(y0 - 0.5f, wsy);
-        const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<ORDER>(z0 - 0.5f, wsz);
+        R wnx[T::NP], wny[T::NP], wnz[T::NP], wsx[T::NP], wsy[T::NP], wsz[T::NP];
+        const int inx = shape_weights<ORDER>(x0, wnx), isx = shape_weights<ORDER>(x0 - R(0.5), wsx);
+        const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<ORDER>(y0 - R(0.5), wsy);
+        const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<ORDER>(z0 - R(0.5), wsz);
         // tile index of the node-centred first node; the staggered components
         // differ from it by one node at most per axis (the guard offset is 1)
         const int bn = ((inz + 1) * T::GY + (iny + 1)) * T::GX + (inx + 1);
         const int ox_ = isx - inx, oy_ = (isy - iny) * T::GX, oz_ = (isz - inz) * (T::GX * T::GY);
-        const float Ex = interp<ORDER>(&fE[0][bn + ox_], wsx, wny, wnz);
-        const float Ey = interp<ORDER>(&fE[1][bn + oy_], wnx, wsy, wnz);
-        const float Ez = interp<ORDER>(&fE[2][bn + oz_], wnx, wny, wsz);
-        const float Bx = interp<ORDER>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
-        const float By = interp<ORDER>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
-        const float Bz = interp<ORDER>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
+        const R Ex = interp<ORDER>(&fE[0][bn + ox_], wsx, wny, wnz);
+        const R Ey = interp<ORDER>(&fE[1][bn + oy_], wnx, wsy, wnz);
+        const R Ez = interp<ORDER>(&fE[2][bn + oz_], wnx, wny, wsz);
+        const R Bx = interp<ORDER>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
+        const R By = interp<ORDER>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
+        const R Bz = interp<ORDER>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
 
         // ---- relativistic Boris: half kick, rotation, half kick
-        const float h = q * qm;
-        const float umx = fmaf(h, Ex, ux), umy = fmaf(h, Ey, uy), umz = fmaf(h, Ez, uz);
-        const float hg = h * __builtin_amdgcn_rsqf(1.0f + umx * umx + umy * umy + umz * umz);
-        const float tx = hg * Bx, ty = hg * By, tz = hg * Bz;
-        const float sf = 2.0f * __builtin_amdgcn_rcpf(1.0f + tx * tx + ty * ty + tz * tz);
-        const float upx = umx + (umy * tz - umz * ty);
-        const float upy = umy + (umz * tx - umx * tz);
-        const float upz = umz + (umx * ty - umy * tx);
-        ux = fmaf(h, Ex, umx + sf * (upy * tz - upz * ty));
-        uy = fmaf(h, Ey, umy + sf * (upz * tx - upx * tz));
-        uz = fmaf(h, Ez, umz + sf * (upx * ty - upy * tx));
+        const R h = q * qm;
+        const R umx = rfma(h, Ex, ux), umy = rfma(h, Ey, uy), umz = rfma(h, Ez, uz);
+        const R hg = h * rrsq(R(1) + umx * umx + umy * umy + umz * umz);
+        const R tx = hg * Bx, ty = hg * By, tz = hg * Bz;
+        const R sf = R(2) * rrcp(R(1) + tx * tx + ty * ty + tz * tz);
+        const R upx = umx + (umy * tz - umz * ty);
+        const R upy = umy + (umz * tx - umx * tz);
+        const R upz = umz + (umx * ty - umy * tx);
+        ux = rfma(h, Ex, umx + sf * (upy * tz - upz * ty));
+        uy = rfma(h, Ey, umy + sf * (upz * tx - upx * tz));
+        uz = rfma(h, Ez, umz + sf * (upx * ty - upy * tx));
 
         // ---- move
-        const float ig = __builtin_amdgcn_rsqf(1.0f + ux * ux + uy * uy + uz * uz);
-        const float ddx = cdx * ux * ig, ddy = cdy * uy * ig, ddz = cdz * uz * ig;
-        if (!(fabsf(ddx) < 1.0f && fabsf(ddy) < 1.0f && fabsf(ddz) < 1.0f)) {
+        const R ig = rrsq(R(1) + ux * ux + uy * uy + uz * uz);
+        const R ddx = cdx * ux * ig, ddy = cdy * uy * ig, ddz = cdz * uz * ig;
+        if (!(rabs(ddx) < R(1) && rabs(ddy) < R(1) && rabs(ddz) < R(1))) {
             bad = true;  // a displacement of a cell or more (or NaN): keep the particle where it was
             continue;
         }
-        const float x1 = x0 + ddx, y1 = y0 + ddy, z1 = z0 + ddz;
+        const R x1 = x0 + ddx, y1 = y0 + ddy, z1 = z0 + ddz;
 
         // ---- current: in line when the first shape node is unchanged on every axis
-        const float qw = q * wgt;
-        float w1x[T::NP], w1y[T::NP], w1z[T::NP];
+        const R qw = q * wgt;
+        R w1x[T::NP], w1y[T::NP], w1z[T::NP];
         const int fx1 = shape_weights<ORDER>(x1, w1x);
         const int fy1 = shape_weights<ORDER>(y1, w1y);
         const int fz1 = shape_weights<ORDER>(z1, w1z);
         const bool same = (fx1 == inx) && (fy1 == iny) && (fz1 == inz);
         if (same) {
-            float DSx[T::NP], DSy[T::NP], DSz[T::NP];
+            R DSx[T::NP], DSy[T::NP], DSz[T::NP];
 #pragma unroll
             for (int k = 0; k < T::NP; ++k) {
                 DSx[k] = w1x[k] - wnx[k];
@@ -331,9 +349,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
             qb = __shfl(qb, leader, 64);
             if (!same) {
-                float4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
-                e[0] = make_float4(x0, y0, z0, qw);
-                e[1] = make_float4(x1, y1, z1, 0.0f);
+                R4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
+                e[0] = make4(x0, y0, z0, qw);
+                e[1] = make4(x1, y1, z1, R(0));
             }
         }
 
@@ -342,8 +360,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // over after the frame loop so no wave waits on a global atomic here
         at(px, u) = x1; at(py, u) = y1; at(pz, u) = z1;
         at(pux, u) = ux; at(puy, u) = uy; at(puz, u) = uz;
-        const bool left = (x1 < 0.0f) || (x1 >= (float)SX) || (y1 < 0.0f) || (y1 >= (float)SY) || (z1 < 0.0f) ||
-                          (z1 >= (float)SZ);
+        const bool left = (x1 < R(0)) || (x1 >= (R)SX) || (y1 < R(0)) || (y1 >= (R)SY) || (z1 < R(0)) ||
+                          (z1 >= (R)SZ);
         const unsigned long long lmask = __ballot(left);
         if (lmask) {
             const int leader = __ffsll((long long)lmask) - 1;
@@ -357,9 +375,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 } else {
                     // hole list full (reported through FLAG_MIGRATE below): keep the
                     // particle inside its supercell so every later access stays in bounds
-                    at(px, u) = fminf(fmaxf(x1, 0.0f), XMAX);
-                    at(py, u) = fminf(fmaxf(y1, 0.0f), YMAX);
-                    at(pz, u) = fminf(fmaxf(z1, 0.0f), ZMAX);
+                    at(px, u) = rmin(rmax(x1, R(0)), xm);
+                    at(py, u) = rmin(rmax(y1, R(0)), ym);
+                    at(pz, u) = rmin(rmax(z1, R(0)), zm);
                 }
             }
         }
@@ -370,11 +388,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // ---- queued particles: general (ORDER+2)-node window, all lanes busy
     const int nq = s_queue;
     for (int t = tid; t < nq; t += NT) {
-        const float4* e = g.qbuf + 2 * (qbase + t);
-        const float4 a = e[0], b = e[1];
-        const float x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
-        const float x1 = b.x, y1 = b.y, z1 = b.z;
-        float S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
+        const R4* e = g.qbuf + 2 * (qbase + t);
+        const R4 a = e[0], b = e[1];
+        const R x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
+        const R x1 = b.x, y1 = b.y, z1 = b.z;
+        R S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
         const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + T::JL;
         const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
         const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
@@ -386,10 +404,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (int t = tid; t < nh; t += NT) {
         const int slot = s.holes[(int64_t)sc * s.cap_in + t];
         const int64_t p = base + slot;
-        const float x1 = s.x[p], y1 = s.y[p], z1 = s.z[p];
-        const int mvx = (x1 < 0.0f) ? -1 : (x1 >= (float)SX ? 1 : 0);
-        const int mvy = (y1 < 0.0f) ? -1 : (y1 >= (float)SY ? 1 : 0);
-        const int mvz = (z1 < 0.0f) ? -1 : (z1 >= (float)SZ ? 1 : 0);
+        const R x1 = s.x[p], y1 = s.y[p], z1 = s.z[p];
+        const int mvx = (x1 < R(0)) ? -1 : (x1 >= (R)SX ? 1 : 0);
+        const int mvy = (y1 < R(0)) ? -1 : (y1 >= (R)SY ? 1 : 0);
+        const int mvz = (z1 < R(0)) ? -1 : (z1 >= (R)SZ ? 1 : 0);
         int dx_ = scx + mvx, dy_ = scy + mvy, dz_ = scz + mvz;
         dx_ += (dx_ < 0) ? g.ncx : 0; dx_ -= (dx_ >= g.ncx) ? g.ncx : 0;
         dy_ += (dy_ < 0) ? g.ncy : 0; dy_ -= (dy_ >= g.ncy) ? g.ncy : 0;
@@ -399,9 +417,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (k < s.cap_in) {
             const int64_t q_ = inbox_index(s, g.nsc, wpar, dest, k);
             // shift into the destination's frame; x - (-8) can round up onto the far face
-            s.ix[q_] = fminf(x1 - (float)(mvx * SX), XMAX);
-            s.iy[q_] = fminf(y1 - (float)(mvy * SY), YMAX);
-            s.iz[q_] = fminf(z1 - (float)(mvz * SZ), ZMAX);
+            s.ix[q_] = rmin(x1 - (R)(mvx * SX), xm);
+            s.iy[q_] = rmin(y1 - (R)(mvy * SY), ym);
+            s.iz[q_] = rmin(z1 - (R)(mvz * SZ), zm);
             s.iux[q_] = s.ux[p]; s.iuy[q_] = s.uy[p]; s.iuz[q_] = s.uz[p];
             s.iw[q_] = s.w[p];
             s.iid[q_] = s.id[p];
@@ -422,8 +440,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int gi = gx + g.nx * (gy + g.ny * gz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long long iv = (long long)tJ[c * T::JN + t];
-            if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+            if constexpr (std::is_same<R, float>::value) {
+                const long long iv = (long long)tJ[c * T::JN + t];
+                if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+            } else {
+                const double v = tJ[c * T::JN + t];
+                if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
+            }
         }
     }
     if (tid == 0) {
@@ -433,24 +456,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, int apar, int wpar,
+template <class R>
+hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double vmax, int apar, int wpar,
                        hipStream_t st)
 {
     if (s.cap > g.qcap) return hipErrorInvalidValue;  // the deposit queue must hold a full supercell
     if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
     const dim3 grid(g.nsc);
     const bool hz = s.zs != nullptr;
-    // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
-    const float jscale = vmax > 0.0f ? 1073741824.0f / vmax : 1.0f;
-    const float jinv = 1.0f / jscale;
+    R jscale = R(1), jinv = R(1);
+    if constexpr (std::is_same<R, float>::value) {
+        // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
+        const float vf = (float)vmax;
+        jscale = vf > 0.0f ? 1073741824.0f / vf : 1.0f;
+        jinv = 1.0f / jscale;
+    }
     if (order == 1) {
-        if (hz) hipLaunchKernelGGL((k_push<1, true, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<1, false, 256>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
+        if (hz) hipLaunchKernelGGL((k_push<1, true, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<1, false, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
     } else {
-        if (hz) hipLaunchKernelGGL((k_push<2, true, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<2, false, 512>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
+        if (hz) hipLaunchKernelGGL((k_push<2, true, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<2, false, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
     }
     return hipGetLastError();
 }
+
+template hipError_t launch_push<float>(const GridView&, const SpeciesView&, int, double, int, int, hipStream_t);
+template hipError_t launch_push<double>(const GridView64&, const SpeciesView64&, int, double, int, int, hipStream_t);
 
 }  // namespace pic

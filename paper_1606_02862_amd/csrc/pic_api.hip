@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pic_internal.hpp"
@@ -20,7 +22,9 @@ struct pic_ctx {
     int order = 1;
     int nsp = 0;
     Species sp[PIC_MAX_SPECIES];
-    GridView g{};
+    GridView g{};          // geometry always; FP32 field pointers in FP32 mode
+    GridView64 g64{};      // FP64 mode: geometry and field pointers
+    bool fp64 = false;
     DiagBuffers diag{};
     hipStream_t stream = nullptr;
     pic_alloc_t alloc{};
@@ -139,6 +143,8 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
         if (!std::isfinite(g->b0[d])) return fail(nullptr, PIC_ERR_ARG, "b0 must be finite");
     if (!std::isfinite(g->rho_bg)) return fail(nullptr, PIC_ERR_ARG, "rho_bg must be finite");
     if (shape != PIC_SHAPE_CIC && shape != PIC_SHAPE_TSC) return fail(nullptr, PIC_ERR_ARG, "unknown shape %d", (int)shape);
+    if (g->precision != PIC_PRECISION_FP32 && g->precision != PIC_PRECISION_FP64)
+        return fail(nullptr, PIC_ERR_ARG, "unknown precision %d", (int)g->precision);
     if (n < 1 || n > PIC_MAX_SPECIES) return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..%d", PIC_MAX_SPECIES);
     double ids = 0.0;
     for (int s = 0; s < n; ++s) {
@@ -171,6 +177,8 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
         if (p.ionize_into != -1) {
             if (p.ionize_into < 0 || p.ionize_into >= n || p.ionize_into == s || p.z_max == 0)
                 return fail(nullptr, PIC_ERR_ARG, "species %d: bad ionize_into", s);
+            if (g->precision == PIC_PRECISION_FP64)
+                return fail(nullptr, PIC_ERR_ARG, "species %d: ionisation runs in FP32 only", s);
             if (sp[p.ionize_into].z_max != 0) return fail(nullptr, PIC_ERR_ARG, "species %d: ionize_into target has charge states", s);
         }
         if (p.cap_ppc < 0 || p.cap_ppc > 8192) return fail(nullptr, PIC_ERR_ARG, "species %d: cap_ppc", s);
@@ -181,6 +189,26 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
     if (ids >= 4294967295.0) return fail(nullptr, PIC_ERR_ARG, "particle ids would not fit in 32 bits");
     return PIC_OK;
 }
+
+// Frames and arrival lists of the real arrays of one species, in R.
+template <class R>
+int alloc_real_arrays(pic_ctx* c, int s, SpeciesViewT<R>& v, size_t n, size_t ni)
+{
+    R** fl[] = {&v.x, &v.y, &v.z, &v.ux, &v.uy, &v.uz, &v.w};
+    for (R** f : fl)
+        if (!(*f = (R*)dev_alloc(c, n * sizeof(R)))) return fail(c, PIC_ERR_OOM, "species %d: frames", s);
+    R** fi[] = {&v.ix, &v.iy, &v.iz, &v.iux, &v.iuy, &v.iuz, &v.iw};
+    for (R** f : fi)
+        if (!(*f = (R*)dev_alloc(c, ni * sizeof(R)))) return fail(c, PIC_ERR_OOM, "species %d: arrivals", s);
+    return PIC_OK;
+}
+
+template <class R> GridViewT<R>& gview(pic_ctx* c);
+template <> GridView& gview<float>(pic_ctx* c) { return c->g; }
+template <> GridView64& gview<double>(pic_ctx* c) { return c->g64; }
+template <class R> SpeciesViewT<R>& sview(pic_ctx* c, int s);
+template <> SpeciesView& sview<float>(pic_ctx* c, int s) { return c->sp[s].v; }
+template <> SpeciesView64& sview<double>(pic_ctx* c, int s) { return c->sp[s].v64; }
 
 int alloc_species(pic_ctx* c, int s)
 {
@@ -196,9 +224,8 @@ int alloc_species(pic_ctx* c, int s)
     cap_in = std::min(cap_in, c->order == 1 ? 2048 : MAX_MIGRATE);  // what the particle kernel's LDS can absorb
     v.cap_in = cap_in;
     const size_t n = (size_t)nsc * v.cap, ni = (size_t)2 * nsc * cap_in;  // two step parities
-    float** fl[] = {&v.x, &v.y, &v.z, &v.ux, &v.uy, &v.uz, &v.w};
-    for (float** f : fl)
-        if (!(*f = (float*)dev_alloc(c, n * 4))) return fail(c, PIC_ERR_OOM, "species %d: frames", s);
+    const int rc = c->fp64 ? alloc_real_arrays(c, s, S.v64, n, ni) : alloc_real_arrays(c, s, v, n, ni);
+    if (rc) return rc;
     if (!(v.id = (uint32_t*)dev_alloc(c, n * 4))) return fail(c, PIC_ERR_OOM, "species %d: ids", s);
     v.zs = nullptr;
     v.izs = nullptr;
@@ -206,9 +233,6 @@ int alloc_species(pic_ctx* c, int s)
         if (!(v.zs = (uint8_t*)dev_alloc(c, n))) return fail(c, PIC_ERR_OOM, "species %d: charge states", s);
         if (!(v.izs = (uint8_t*)dev_alloc(c, ni))) return fail(c, PIC_ERR_OOM, "species %d: arrivals", s);
     }
-    float** fi[] = {&v.ix, &v.iy, &v.iz, &v.iux, &v.iuy, &v.iuz, &v.iw};
-    for (float** f : fi)
-        if (!(*f = (float*)dev_alloc(c, ni * 4))) return fail(c, PIC_ERR_OOM, "species %d: arrivals", s);
     if (!(v.iid = (uint32_t*)dev_alloc(c, ni * 4))) return fail(c, PIC_ERR_OOM, "species %d: arrivals", s);
     if (!(v.holes = (int32_t*)dev_alloc(c, ni * 4))) return fail(c, PIC_ERR_OOM, "species %d: holes", s);
     if (!(v.count = (int32_t*)dev_alloc(c, (size_t)nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
@@ -216,6 +240,13 @@ int alloc_species(pic_ctx* c, int s)
     if (!(v.hole_count = (int32_t*)dev_alloc(c, (size_t)nsc * 4))) return fail(c, PIC_ERR_OOM, "species %d: counts", s);
     v.charge = (float)d.charge;
     v.mass = (float)d.mass;
+    // the FP64 view shares every integer array and size
+    SpeciesView64& w = S.v64;
+    w.id = v.id; w.zs = v.zs; w.count = v.count; w.cap = v.cap;
+    w.iid = v.iid; w.izs = v.izs; w.in_count = v.in_count; w.holes = v.holes; w.hole_count = v.hole_count;
+    w.cap_in = v.cap_in;
+    w.charge = d.charge;
+    w.mass = d.mass;
     HIPCHK(c, launch_zero_i32(v.count, nsc, c->stream));
     HIPCHK(c, launch_zero_i32(v.in_count, 2 * nsc, c->stream));
     HIPCHK(c, launch_zero_i32(v.hole_count, nsc, c->stream));
@@ -299,15 +330,19 @@ int read_flags(pic_ctx* c)
     return PIC_OK;
 }
 
-int mark_reference(pic_ctx* c)
+template <class R>
+int mark_reference_t(pic_ctx* c)
 {
     const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
     HIPCHK(c, launch_zero_f64(c->diag.rho, N, c->stream));
-    for (int s = 0; s < c->nsp; ++s) HIPCHK(c, launch_rho_deposit(c->g, c->sp[s].v, c->order, c->diag.rho, c->stream));
-    HIPCHK(c, launch_gauss(c->g, c->diag, c->grid.rho_bg, 0, c->stream));
+    for (int s = 0; s < c->nsp; ++s)
+        HIPCHK(c, launch_rho_deposit<R>(gview<R>(c), sview<R>(c, s), c->order, c->diag.rho, c->stream));
+    HIPCHK(c, launch_gauss<R>(gview<R>(c), c->diag, c->grid.rho_bg, 0, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
+
+int mark_reference(pic_ctx* c) { return c->fp64 ? mark_reference_t<double>(c) : mark_reference_t<float>(c); }
 
 hipEvent_t next_event(pic_ctx* c)
 {
@@ -361,6 +396,222 @@ int64_t host_count(pic_ctx* c, int s, std::vector<int32_t>& counts)
     return t;
 }
 
+// Particle and field transfers, templated on the device real type R and the
+// host view (FP32 or FP64 momenta and weights).
+template <class R, class V>
+int get_particles_t(pic_ctx* c, int s, V* v)
+{
+    using U = typename std::remove_pointer<decltype(v->ux)>::type;
+    const SpeciesViewT<R>& sv = sview<R>(c, s);
+    std::vector<int32_t> cnt;
+    const int64_t total = host_count(c, s, cnt);
+    if (total < 0) return fail(c, PIC_ERR_HIP, "count readback failed");
+    v->count = total;
+    if (!v->x || !v->y || !v->z || !v->ux || !v->uy || !v->uz || !v->w || !v->id)
+        return fail(c, PIC_ERR_ARG, "view arrays must not be NULL");
+    if (v->capacity < total) return fail(c, PIC_ERR_ARG, "view capacity %lld < %lld particles", (long long)v->capacity, (long long)total);
+    const size_t n = (size_t)c->g.nsc * sv.cap;
+    std::vector<R> a[7];
+    const R* src[7] = {sv.x, sv.y, sv.z, sv.ux, sv.uy, sv.uz, sv.w};
+    for (int k = 0; k < 7; ++k) {
+        a[k].resize(n);
+        HIPCHK(c, hipMemcpyAsync(a[k].data(), src[k], n * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+    }
+    std::vector<uint32_t> ids(n);
+    std::vector<uint8_t> zs;
+    HIPCHK(c, hipMemcpyAsync(ids.data(), sv.id, n * 4, hipMemcpyDeviceToHost, c->stream));
+    if (sv.zs) {
+        zs.resize(n);
+        HIPCHK(c, hipMemcpyAsync(zs.data(), sv.zs, n, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<size_t> order;
+    order.reserve(total);
+    for (int sc = 0; sc < c->g.nsc; ++sc)
+        for (int t = 0; t < cnt[sc]; ++t) order.push_back((size_t)sc * sv.cap + t);
+    std::sort(order.begin(), order.end(), [&](size_t p, size_t q) { return ids[p] < ids[q]; });
+    for (int64_t k = 0; k < total; ++k) {
+        const size_t p = order[k];
+        const int sc = (int)(p / sv.cap);
+        const int scx = sc % c->g.ncx, scy = (sc / c->g.ncx) % c->g.ncy, scz = sc / (c->g.ncx * c->g.ncy);
+        v->x[k] = (double)(scx * SX) + (double)a[0][p];
+        v->y[k] = (double)(scy * SY) + (double)a[1][p];
+        v->z[k] = (double)(scz * SZ) + (double)a[2][p];
+        v->ux[k] = (U)a[3][p];
+        v->uy[k] = (U)a[4][p];
+        v->uz[k] = (U)a[5][p];
+        v->w[k] = (U)a[6][p];
+        v->id[k] = ids[p];
+        if (v->zstate) v->zstate[k] = sv.zs ? zs[p] : 0;
+    }
+    return PIC_OK;
+}
+
+template <class R, class V>
+int set_particles_t(pic_ctx* c, int s, const V* v)
+{
+    if (v->count < 0) return fail(c, PIC_ERR_ARG, "negative count");
+    if (v->count > 0 && (!v->x || !v->y || !v->z || !v->ux || !v->uy || !v->uz || !v->w || !v->id))
+        return fail(c, PIC_ERR_ARG, "view arrays must not be NULL");
+    const SpeciesViewT<R>& sv = sview<R>(c, s);
+    const GridView& g = c->g;
+    const size_t n = (size_t)g.nsc * sv.cap;
+    std::vector<int32_t> cnt(g.nsc, 0);
+    std::vector<R> a[7];
+    for (auto& x : a) x.assign(n, R(0));
+    std::vector<uint32_t> ids(n, 0);
+    std::vector<uint8_t> zs(sv.zs ? n : 0, 0);
+    const R lim[3] = {face_below<R>((R)SX), face_below<R>((R)SY), face_below<R>((R)SZ)};
+    const double rmax = (double)std::numeric_limits<R>::max();
+    double wmax = 0.0;
+    for (int64_t k = 0; k < v->count; ++k) {
+        const double p[3] = {v->x[k], v->y[k], v->z[k]};
+        const int dims[3] = {g.nx, g.ny, g.nz}, sdim[3] = {SX, SY, SZ};
+        int sci[3];
+        R rel[3];
+        for (int d = 0; d < 3; ++d) {
+            if (!(p[d] >= 0.0 && p[d] < (double)dims[d]))
+                return fail(c, PIC_ERR_ARG, "particle %lld: position %g outside [0,%d)", (long long)k, p[d], dims[d]);
+            sci[d] = (int)std::floor(p[d] / sdim[d]);
+            if (sci[d] >= dims[d] / sdim[d]) sci[d] = dims[d] / sdim[d] - 1;
+            rel[d] = std::min((R)(p[d] - (double)(sci[d] * sdim[d])), lim[d]);
+            if (rel[d] < R(0)) rel[d] = R(0);
+        }
+        const double u[4] = {(double)v->ux[k], (double)v->uy[k], (double)v->uz[k], (double)v->w[k]};
+        for (double x : u)
+            if (!std::isfinite(x) || std::fabs(x) > rmax)
+                return fail(c, PIC_ERR_ARG, "particle %lld: non-finite momentum or weight", (long long)k);
+        if (v->id[k] < 0 || v->id[k] > 0xFFFFFFFFLL) return fail(c, PIC_ERR_ARG, "particle %lld: id out of range", (long long)k);
+        const int sc = sci[0] + g.ncx * (sci[1] + g.ncy * sci[2]);
+        if (cnt[sc] >= sv.cap) return fail(c, PIC_ERR_CAPACITY, "supercell %d holds more than %d particles", sc, sv.cap);
+        wmax = std::max(wmax, std::fabs(u[3]));
+        const size_t q = (size_t)sc * sv.cap + cnt[sc]++;
+        a[0][q] = rel[0]; a[1][q] = rel[1]; a[2][q] = rel[2];
+        a[3][q] = (R)u[0]; a[4][q] = (R)u[1]; a[5][q] = (R)u[2]; a[6][q] = (R)u[3];
+        ids[q] = (uint32_t)v->id[k];
+        if (sv.zs) {
+            const int z = v->zstate ? v->zstate[k] : c->sp[s].desc.z_init;
+            if (z < 0 || z > c->sp[s].desc.z_max) return fail(c, PIC_ERR_ARG, "particle %lld: charge state out of range", (long long)k);
+            zs[q] = (uint8_t)z;
+        }
+    }
+    R* dst[7] = {sv.x, sv.y, sv.z, sv.ux, sv.uy, sv.uz, sv.w};
+    for (int k = 0; k < 7; ++k)
+        HIPCHK(c, hipMemcpyAsync(dst[k], a[k].data(), n * sizeof(R), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sv.id, ids.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+    if (sv.zs) HIPCHK(c, hipMemcpyAsync(sv.zs, zs.data(), n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sv.count, cnt.data(), (size_t)g.nsc * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->sp[s].wmax = wmax;
+    return PIC_OK;
+}
+
+template <class R, class T>
+int get_fields_t(pic_ctx* c, T* E, T* B, T* J)
+{
+    const size_t n3 = (size_t)3 * c->grid.nx * c->grid.ny * c->grid.nz;
+    const GridViewT<R>& g = gview<R>(c);
+    const R* src[3] = {g.E, g.B, g.J};
+    T* dst[3] = {E, B, J};
+    std::vector<R> tmp;
+    for (int f = 0; f < 3; ++f) {
+        if (!dst[f]) continue;
+        if constexpr (std::is_same<R, T>::value) {
+            HIPCHK(c, hipMemcpyAsync(dst[f], src[f], n3 * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            tmp.resize(n3);
+            HIPCHK(c, hipMemcpyAsync(tmp.data(), src[f], n3 * sizeof(R), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (size_t i = 0; i < n3; ++i) dst[f][i] = (T)tmp[i];
+        }
+    }
+    return PIC_OK;
+}
+
+template <class R, class T>
+int set_fields_t(pic_ctx* c, const T* E, const T* B, const T* J)
+{
+    const size_t n3 = (size_t)3 * c->grid.nx * c->grid.ny * c->grid.nz;
+    const double rmax = (double)std::numeric_limits<R>::max();
+    const T* src[3] = {E, B, J};
+    for (const T* f : src)
+        if (f)
+            for (size_t i = 0; i < n3; ++i)
+                if (!std::isfinite((double)f[i]) || std::fabs((double)f[i]) > rmax)
+                    return fail(c, PIC_ERR_ARG, "non-finite field value at %zu", i);
+    const GridViewT<R>& g = gview<R>(c);
+    R* dst[3] = {g.E, g.B, g.J};
+    std::vector<R> tmp;
+    for (int f = 0; f < 3; ++f) {
+        if (!src[f]) continue;
+        if constexpr (std::is_same<R, T>::value) {
+            HIPCHK(c, hipMemcpyAsync(dst[f], src[f], n3 * sizeof(R), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            tmp.resize(n3);
+            for (size_t i = 0; i < n3; ++i) tmp[i] = (R)src[f][i];
+            HIPCHK(c, hipMemcpyAsync(dst[f], tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    return PIC_OK;
+}
+
+// The cycles of pic_step in real type R.
+template <class R>
+int step_t(pic_ctx* c, int n)
+{
+    GridViewT<R>& g = gview<R>(c);
+    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    const double dt = c->grid.dt;
+    for (int it = 0; it < n; ++it) {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+        if (c->timing) {
+            e0 = next_event(c); e1 = next_event(c); e2 = next_event(c); e3 = next_event(c);
+            if (!e0 || !e1 || !e2 || !e3) return fail(c, PIC_ERR_HIP, "event creation failed");
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+        }
+        HIPCHK(c, launch_zero_r(g.J, 3 * N, c->stream));
+        // step `it` writes its leavers to parity it & 1 and absorbs the previous step's
+        const int wpar = it & 1, apar = it > 0 ? ((it - 1) & 1) : -1;
+        for (int s = 0; s < c->nsp; ++s) {
+            if (!c->sp[s].desc.mobile) continue;
+            HIPCHK(c, launch_push<R>(g, sview<R>(c, s), c->order, push_vmax(c, s), apar, wpar, c->stream));
+            c->pending_launches += c->timing ? 1 : 0;
+        }
+        if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+        if (it == n - 1)  // last step of the call: leave the frames dense
+            for (int s = 0; s < c->nsp; ++s) {
+                if (!c->sp[s].desc.mobile) continue;
+                HIPCHK(c, launch_migrate<R>(g, sview<R>(c, s), wpar, c->stream));
+            }
+        if (c->timing) HIPCHK(c, hipEventRecord(e2, c->stream));
+        HIPCHK(c, launch_yee_b<R>(g, 0.5 * dt, c->stream));
+        HIPCHK(c, launch_yee_e<R>(g, dt, c->stream));
+        HIPCHK(c, launch_yee_b<R>(g, 0.5 * dt, c->stream));
+        if (c->timing) HIPCHK(c, hipEventRecord(e3, c->stream));
+        ++c->step;
+    }
+    return PIC_OK;
+}
+
+// FP64 diagnostics of the state in real type R (results in diag.result).
+template <class R>
+int moments_t(pic_ctx* c)
+{
+    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    GridViewT<R>& g = gview<R>(c);
+    HIPCHK(c, launch_zero_f64(c->diag.result, D_NSLOTS, c->stream));
+    HIPCHK(c, launch_field_energy<R>(g, c->diag, c->stream));
+    for (int s = 0; s < c->nsp; ++s) HIPCHK(c, launch_kinetic<R>(g, sview<R>(c, s), c->diag, s, c->stream));
+    HIPCHK(c, launch_zero_f64(c->diag.rho, N, c->stream));
+    for (int s = 0; s < c->nsp; ++s)
+        HIPCHK(c, launch_rho_deposit<R>(g, sview<R>(c, s), c->order, c->diag.rho, c->stream));
+    HIPCHK(c, launch_gauss<R>(g, c->diag, c->grid.rho_bg, 1, c->stream));
+    return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -394,6 +645,14 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     g.xcd_remap = (g.nsc % 8 == 0) ? 1 : 0;
     g.dx = (float)grid->dx; g.dy = (float)grid->dy; g.dz = (float)grid->dz; g.dt = (float)grid->dt;
     g.b0x = (float)grid->b0[0]; g.b0y = (float)grid->b0[1]; g.b0z = (float)grid->b0[2];
+    c->fp64 = grid->precision == PIC_PRECISION_FP64;
+    GridView64& g64 = c->g64;
+    g64.nx = g.nx; g64.ny = g.ny; g64.nz = g.nz;
+    g64.ncx = g.ncx; g64.ncy = g.ncy; g64.ncz = g.ncz;
+    g64.nsc = g.nsc;
+    g64.xcd_remap = g.xcd_remap;
+    g64.dx = grid->dx; g64.dy = grid->dy; g64.dz = grid->dz; g64.dt = grid->dt;
+    g64.b0x = grid->b0[0]; g64.b0y = grid->b0[1]; g64.b0z = grid->b0[2];
     const int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
 
     auto bail = [&](int code) {
@@ -408,8 +667,15 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         c->err = "pinned host allocation failed";
         return bail(PIC_ERR_HIP);
     }
-    if (!(g.E = (float*)dev_alloc(c, 3 * N * 4)) || !(g.B = (float*)dev_alloc(c, 3 * N * 4)) ||
-        !(g.J = (float*)dev_alloc(c, 3 * N * 4)) || !(g.flags = (int32_t*)dev_alloc(c, 64))) {
+    bool fields_ok = (g.flags = (int32_t*)dev_alloc(c, 64)) != nullptr;
+    if (c->fp64)
+        fields_ok = fields_ok && (g64.E = (double*)dev_alloc(c, 3 * N * 8)) && (g64.B = (double*)dev_alloc(c, 3 * N * 8)) &&
+                    (g64.J = (double*)dev_alloc(c, 3 * N * 8));
+    else
+        fields_ok = fields_ok && (g.E = (float*)dev_alloc(c, 3 * N * 4)) && (g.B = (float*)dev_alloc(c, 3 * N * 4)) &&
+                    (g.J = (float*)dev_alloc(c, 3 * N * 4));
+    g64.flags = g.flags;
+    if (!fields_ok) {
         c->err = "device allocation of fields failed";
         return bail(PIC_ERR_OOM);
     }
@@ -420,9 +686,12 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         c->err = "device allocation of diagnostics failed";
         return bail(PIC_ERR_OOM);
     }
-    if (launch_zero_f32(g.E, 3 * N, c->stream) || launch_zero_f32(g.B, 3 * N, c->stream) ||
-        launch_zero_f32(g.J, 3 * N, c->stream) || launch_zero_i32(g.flags, 16, c->stream) ||
-        launch_zero_f64(c->diag.result, D_NSLOTS, c->stream)) {
+    const bool zero_failed =
+        c->fp64 ? (launch_zero_f64(g64.E, 3 * N, c->stream) || launch_zero_f64(g64.B, 3 * N, c->stream) ||
+                   launch_zero_f64(g64.J, 3 * N, c->stream))
+                : (launch_zero_f32(g.E, 3 * N, c->stream) || launch_zero_f32(g.B, 3 * N, c->stream) ||
+                   launch_zero_f32(g.J, 3 * N, c->stream));
+    if (zero_failed || launch_zero_i32(g.flags, 16, c->stream) || launch_zero_f64(c->diag.result, D_NSLOTS, c->stream)) {
         c->err = "field initialisation launch failed";
         return bail(PIC_ERR_HIP);
     }
@@ -444,7 +713,10 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     // one deposit queue shared by the species (their particle kernels run one after another)
     g.qcap = 0;
     for (int s = 0; s < n_species; ++s) g.qcap = std::max(g.qcap, c->sp[s].v.cap);
-    if (!(g.qbuf = (float4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(float4)))) {
+    g64.qcap = g.qcap;
+    const bool q_ok = c->fp64 ? (g64.qbuf = (double4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(double4))) != nullptr
+                              : (g.qbuf = (float4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(float4))) != nullptr;
+    if (!q_ok) {
         c->err = "device allocation of the deposit queue failed";
         return bail(PIC_ERR_OOM);
     }
@@ -456,8 +728,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         const double b2 = d.drift_beta[0] * d.drift_beta[0] + d.drift_beta[1] * d.drift_beta[1] +
                           d.drift_beta[2] * d.drift_beta[2];
         const double gam = 1.0 / std::sqrt(1.0 - b2);
-        const float drift_u[3] = {(float)(gam * d.drift_beta[0]), (float)(gam * d.drift_beta[1]),
-                                  (float)(gam * d.drift_beta[2])};
+        const double drift_u[3] = {gam * d.drift_beta[0], gam * d.drift_beta[1], gam * d.drift_beta[2]};
         int pos_index = s, pos_ppc = d.ppc;
         int64_t pos_off = S.id_offset;
         if (d.coincident_with >= 0) {
@@ -465,8 +736,12 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
             pos_ppc = c->sp[pos_index].desc.ppc;
             pos_off = c->sp[pos_index].id_offset;
         }
-        if (launch_init_species(g, S.v, grid->seed, s, d.ppc, S.id_offset, pos_index, pos_ppc, pos_off, (float)d.u_th,
-                                drift_u, d.layout, (float)S.weight, d.z_init, c->stream) != hipSuccess) {
+        const hipError_t e =
+            c->fp64 ? launch_init_species<double>(g64, S.v64, grid->seed, s, d.ppc, S.id_offset, pos_index, pos_ppc,
+                                                  pos_off, d.u_th, drift_u, d.layout, S.weight, d.z_init, c->stream)
+                    : launch_init_species<float>(g, S.v, grid->seed, s, d.ppc, S.id_offset, pos_index, pos_ppc, pos_off,
+                                                 d.u_th, drift_u, d.layout, S.weight, d.z_init, c->stream);
+        if (e != hipSuccess) {
             c->err = "init launch failed";
             return bail(PIC_ERR_HIP);
         }
@@ -489,36 +764,8 @@ int pic_step(pic_ctx* c, int n)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (n < 0) return fail(c, PIC_ERR_ARG, "n must be >= 0");
-    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
-    const float dt = (float)c->grid.dt;
-    for (int it = 0; it < n; ++it) {
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-        if (c->timing) {
-            e0 = next_event(c); e1 = next_event(c); e2 = next_event(c); e3 = next_event(c);
-            if (!e0 || !e1 || !e2 || !e3) return fail(c, PIC_ERR_HIP, "event creation failed");
-            HIPCHK(c, hipEventRecord(e0, c->stream));
-        }
-        HIPCHK(c, launch_zero_f32(c->g.J, 3 * N, c->stream));
-        // step `it` writes its leavers to parity it & 1 and absorbs the previous step's
-        const int wpar = it & 1, apar = it > 0 ? ((it - 1) & 1) : -1;
-        for (int s = 0; s < c->nsp; ++s) {
-            if (!c->sp[s].desc.mobile) continue;
-            HIPCHK(c, launch_push(c->g, c->sp[s].v, c->order, (float)push_vmax(c, s), apar, wpar, c->stream));
-            c->pending_launches += c->timing ? 1 : 0;
-        }
-        if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
-        if (it == n - 1)  // last step of the call: leave the frames dense
-            for (int s = 0; s < c->nsp; ++s) {
-                if (!c->sp[s].desc.mobile) continue;
-                HIPCHK(c, launch_migrate(c->g, c->sp[s].v, wpar, c->stream));
-            }
-        if (c->timing) HIPCHK(c, hipEventRecord(e2, c->stream));
-        HIPCHK(c, launch_yee_b(c->g, 0.5f * dt, c->stream));
-        HIPCHK(c, launch_yee_e(c->g, dt, c->stream));
-        HIPCHK(c, launch_yee_b(c->g, 0.5f * dt, c->stream));
-        if (c->timing) HIPCHK(c, hipEventRecord(e3, c->stream));
-        ++c->step;
-    }
+    const int rc0 = c->fp64 ? step_t<double>(c, n) : step_t<float>(c, n);
+    if (rc0) return rc0;
     if (c->timing) {
         // particles processed: counts before the step are what each push launch read
         for (int s = 0; s < c->nsp; ++s)
@@ -558,13 +805,8 @@ int pic_mark_reference(pic_ctx* c)
 int pic_moments(pic_ctx* c, pic_moments_t* out)
 {
     if (!c || !out) return fail(c, PIC_ERR_ARG, "ctx and out must not be NULL");
-    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
-    HIPCHK(c, launch_zero_f64(c->diag.result, D_NSLOTS, c->stream));
-    HIPCHK(c, launch_field_energy(c->g, c->diag, c->stream));
-    for (int s = 0; s < c->nsp; ++s) HIPCHK(c, launch_kinetic(c->g, c->sp[s].v, c->diag, s, c->stream));
-    HIPCHK(c, launch_zero_f64(c->diag.rho, N, c->stream));
-    for (int s = 0; s < c->nsp; ++s) HIPCHK(c, launch_rho_deposit(c->g, c->sp[s].v, c->order, c->diag.rho, c->stream));
-    HIPCHK(c, launch_gauss(c->g, c->diag, c->grid.rho_bg, 1, c->stream));
+    const int rc = c->fp64 ? moments_t<double>(c) : moments_t<float>(c);
+    if (rc) return rc;
     double r[D_NSLOTS];
     HIPCHK(c, hipMemcpyAsync(r, c->diag.result, sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -603,131 +845,52 @@ int pic_get_particles(pic_ctx* c, int s, pic_particles_view_t* v)
 {
     if (!c || !v) return fail(c, PIC_ERR_ARG, "ctx and view must not be NULL");
     if (s < 0 || s >= c->nsp) return fail(c, PIC_ERR_ARG, "species %d out of range", s);
-    const SpeciesView& sv = c->sp[s].v;
-    std::vector<int32_t> cnt;
-    const int64_t total = host_count(c, s, cnt);
-    if (total < 0) return fail(c, PIC_ERR_HIP, "count readback failed");
-    v->count = total;
-    if (!v->x || !v->y || !v->z || !v->ux || !v->uy || !v->uz || !v->w || !v->id)
-        return fail(c, PIC_ERR_ARG, "view arrays must not be NULL");
-    if (v->capacity < total) return fail(c, PIC_ERR_ARG, "view capacity %lld < %lld particles", (long long)v->capacity, (long long)total);
-    const size_t n = (size_t)c->g.nsc * sv.cap;
-    std::vector<float> a[7];
-    const float* src[7] = {sv.x, sv.y, sv.z, sv.ux, sv.uy, sv.uz, sv.w};
-    for (int k = 0; k < 7; ++k) {
-        a[k].resize(n);
-        HIPCHK(c, hipMemcpyAsync(a[k].data(), src[k], n * 4, hipMemcpyDeviceToHost, c->stream));
-    }
-    std::vector<uint32_t> ids(n);
-    std::vector<uint8_t> zs;
-    HIPCHK(c, hipMemcpyAsync(ids.data(), sv.id, n * 4, hipMemcpyDeviceToHost, c->stream));
-    if (sv.zs) {
-        zs.resize(n);
-        HIPCHK(c, hipMemcpyAsync(zs.data(), sv.zs, n, hipMemcpyDeviceToHost, c->stream));
-    }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<size_t> order;
-    order.reserve(total);
-    for (int sc = 0; sc < c->g.nsc; ++sc)
-        for (int t = 0; t < cnt[sc]; ++t) order.push_back((size_t)sc * sv.cap + t);
-    std::sort(order.begin(), order.end(), [&](size_t p, size_t q) { return ids[p] < ids[q]; });
-    for (int64_t k = 0; k < total; ++k) {
-        const size_t p = order[k];
-        const int sc = (int)(p / sv.cap);
-        const int scx = sc % c->g.ncx, scy = (sc / c->g.ncx) % c->g.ncy, scz = sc / (c->g.ncx * c->g.ncy);
-        v->x[k] = (double)(scx * SX) + (double)a[0][p];
-        v->y[k] = (double)(scy * SY) + (double)a[1][p];
-        v->z[k] = (double)(scz * SZ) + (double)a[2][p];
-        v->ux[k] = a[3][p];
-        v->uy[k] = a[4][p];
-        v->uz[k] = a[5][p];
-        v->w[k] = a[6][p];
-        v->id[k] = ids[p];
-        if (v->zstate) v->zstate[k] = sv.zs ? zs[p] : 0;
-    }
-    return PIC_OK;
+    return c->fp64 ? get_particles_t<double>(c, s, v) : get_particles_t<float>(c, s, v);
+}
+
+int pic_get_particles64(pic_ctx* c, int s, pic_particles64_view_t* v)
+{
+    if (!c || !v) return fail(c, PIC_ERR_ARG, "ctx and view must not be NULL");
+    if (s < 0 || s >= c->nsp) return fail(c, PIC_ERR_ARG, "species %d out of range", s);
+    return c->fp64 ? get_particles_t<double>(c, s, v) : get_particles_t<float>(c, s, v);
 }
 
 int pic_set_particles(pic_ctx* c, int s, const pic_particles_view_t* v)
 {
     if (!c || !v) return fail(c, PIC_ERR_ARG, "ctx and view must not be NULL");
     if (s < 0 || s >= c->nsp) return fail(c, PIC_ERR_ARG, "species %d out of range", s);
-    if (v->count < 0) return fail(c, PIC_ERR_ARG, "negative count");
-    if (v->count > 0 && (!v->x || !v->y || !v->z || !v->ux || !v->uy || !v->uz || !v->w || !v->id))
-        return fail(c, PIC_ERR_ARG, "view arrays must not be NULL");
-    const SpeciesView& sv = c->sp[s].v;
-    const GridView& g = c->g;
-    const size_t n = (size_t)g.nsc * sv.cap;
-    std::vector<int32_t> cnt(g.nsc, 0);
-    std::vector<float> a[7];
-    for (auto& x : a) x.assign(n, 0.0f);
-    std::vector<uint32_t> ids(n, 0);
-    std::vector<uint8_t> zs(sv.zs ? n : 0, 0);
-    const float lim[3] = {XMAX, YMAX, ZMAX};
-    double wmax = 0.0;
-    for (int64_t k = 0; k < v->count; ++k) {
-        const double p[3] = {v->x[k], v->y[k], v->z[k]};
-        const int dims[3] = {g.nx, g.ny, g.nz}, sdim[3] = {SX, SY, SZ};
-        int sci[3];
-        float rel[3];
-        for (int d = 0; d < 3; ++d) {
-            if (!(p[d] >= 0.0 && p[d] < (double)dims[d]))
-                return fail(c, PIC_ERR_ARG, "particle %lld: position %g outside [0,%d)", (long long)k, p[d], dims[d]);
-            sci[d] = (int)std::floor(p[d] / sdim[d]);
-            if (sci[d] >= dims[d] / sdim[d]) sci[d] = dims[d] / sdim[d] - 1;
-            rel[d] = std::min((float)(p[d] - (double)(sci[d] * sdim[d])), lim[d]);
-            if (rel[d] < 0.0f) rel[d] = 0.0f;
-        }
-        if (!std::isfinite(v->ux[k]) || !std::isfinite(v->uy[k]) || !std::isfinite(v->uz[k]) || !std::isfinite(v->w[k]))
-            return fail(c, PIC_ERR_ARG, "particle %lld: non-finite momentum or weight", (long long)k);
-        if (v->id[k] < 0 || v->id[k] > 0xFFFFFFFFLL) return fail(c, PIC_ERR_ARG, "particle %lld: id out of range", (long long)k);
-        const int sc = sci[0] + g.ncx * (sci[1] + g.ncy * sci[2]);
-        if (cnt[sc] >= sv.cap) return fail(c, PIC_ERR_CAPACITY, "supercell %d holds more than %d particles", sc, sv.cap);
-        wmax = std::max(wmax, (double)std::fabs(v->w[k]));
-        const size_t q = (size_t)sc * sv.cap + cnt[sc]++;
-        a[0][q] = rel[0]; a[1][q] = rel[1]; a[2][q] = rel[2];
-        a[3][q] = v->ux[k]; a[4][q] = v->uy[k]; a[5][q] = v->uz[k]; a[6][q] = v->w[k];
-        ids[q] = (uint32_t)v->id[k];
-        if (sv.zs) {
-            const int z = v->zstate ? v->zstate[k] : c->sp[s].desc.z_init;
-            if (z < 0 || z > c->sp[s].desc.z_max) return fail(c, PIC_ERR_ARG, "particle %lld: charge state out of range", (long long)k);
-            zs[q] = (uint8_t)z;
-        }
-    }
-    float* dst[7] = {sv.x, sv.y, sv.z, sv.ux, sv.uy, sv.uz, sv.w};
-    for (int k = 0; k < 7; ++k) HIPCHK(c, hipMemcpyAsync(dst[k], a[k].data(), n * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(sv.id, ids.data(), n * 4, hipMemcpyHostToDevice, c->stream));
-    if (sv.zs) HIPCHK(c, hipMemcpyAsync(sv.zs, zs.data(), n, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(sv.count, cnt.data(), (size_t)g.nsc * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->sp[s].wmax = wmax;
-    return PIC_OK;
+    return c->fp64 ? set_particles_t<double>(c, s, v) : set_particles_t<float>(c, s, v);
+}
+
+int pic_set_particles64(pic_ctx* c, int s, const pic_particles64_view_t* v)
+{
+    if (!c || !v) return fail(c, PIC_ERR_ARG, "ctx and view must not be NULL");
+    if (s < 0 || s >= c->nsp) return fail(c, PIC_ERR_ARG, "species %d out of range", s);
+    return c->fp64 ? set_particles_t<double>(c, s, v) : set_particles_t<float>(c, s, v);
 }
 
 int pic_get_fields(pic_ctx* c, float* E, float* B, float* J)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
-    const size_t bytes = (size_t)3 * c->grid.nx * c->grid.ny * c->grid.nz * 4;
-    if (E) HIPCHK(c, hipMemcpyAsync(E, c->g.E, bytes, hipMemcpyDeviceToHost, c->stream));
-    if (B) HIPCHK(c, hipMemcpyAsync(B, c->g.B, bytes, hipMemcpyDeviceToHost, c->stream));
-    if (J) HIPCHK(c, hipMemcpyAsync(J, c->g.J, bytes, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PIC_OK;
+    return c->fp64 ? get_fields_t<double>(c, E, B, J) : get_fields_t<float>(c, E, B, J);
+}
+
+int pic_get_fields64(pic_ctx* c, double* E, double* B, double* J)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    return c->fp64 ? get_fields_t<double>(c, E, B, J) : get_fields_t<float>(c, E, B, J);
 }
 
 int pic_set_fields(pic_ctx* c, const float* E, const float* B, const float* J)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
-    const size_t n3 = (size_t)3 * c->grid.nx * c->grid.ny * c->grid.nz;
-    for (const float* f : {E, B, J})
-        if (f)
-            for (size_t i = 0; i < n3; ++i)
-                if (!std::isfinite(f[i])) return fail(c, PIC_ERR_ARG, "non-finite field value at %zu", i);
-    if (E) HIPCHK(c, hipMemcpyAsync(c->g.E, E, n3 * 4, hipMemcpyHostToDevice, c->stream));
-    if (B) HIPCHK(c, hipMemcpyAsync(c->g.B, B, n3 * 4, hipMemcpyHostToDevice, c->stream));
-    if (J) HIPCHK(c, hipMemcpyAsync(c->g.J, J, n3 * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PIC_OK;
+    return c->fp64 ? set_fields_t<double>(c, E, B, J) : set_fields_t<float>(c, E, B, J);
+}
+
+int pic_set_fields64(pic_ctx* c, const double* E, const double* B, const double* J)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    return c->fp64 ? set_fields_t<double>(c, E, B, J) : set_fields_t<float>(c, E, B, J);
 }
 
 int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)

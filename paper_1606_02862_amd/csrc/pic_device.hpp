@@ -48,26 +48,47 @@ enum Purpose {
     PURPOSE_MLP_INIT = 5    // initial weights
 };
 
+// ---------------------------------------------------------------- real type
+// Overloads for the templated PIC kernels (R = float or double).  1/sqrt and
+// 1/x are the hardware approximations in FP32 (the push stays within its
+// parity bound by a wide margin) and IEEE sqrt and division in FP64.
+__device__ inline float rfloor(float x) { return floorf(x); }
+__device__ inline double rfloor(double x) { return floor(x); }
+__device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float rabs(float x) { return fabsf(x); }
+__device__ inline double rabs(double x) { return fabs(x); }
+__device__ inline float rmin(float a, float b) { return fminf(a, b); }
+__device__ inline double rmin(double a, double b) { return fmin(a, b); }
+__device__ inline float rmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double rmax(double a, double b) { return fmax(a, b); }
+__device__ inline float rrsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rrsq(double x) { return 1.0 / sqrt(x); }
+__device__ inline float rrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rrcp(double x) { return 1.0 / x; }
+__device__ inline float4 make4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+__device__ inline double4 make4(double a, double b, double c, double d) { return make_double4(a, b, c, d); }
+
 // ---------------------------------------------------------------- shapes
 // CIC: nodes f, f+1 with f = floor(x); weights 1-d, d (d = x - f).
 // TSC: nodes r-1, r, r+1 with r = floor(x + 1/2); d = x - r in [-1/2, 1/2):
 //      1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2.
-template <int ORDER>
-__device__ inline int shape_weights(float x, float* w)
+template <int ORDER, class R>
+__device__ inline int shape_weights(R x, R* w)
 {
     if constexpr (ORDER == 1) {
-        const float f = floorf(x);
-        const float d = x - f;
-        w[0] = 1.0f - d;
+        const R f = rfloor(x);
+        const R d = x - f;
+        w[0] = R(1) - d;
         w[1] = d;
         return (int)f;
     } else {
-        const float r = floorf(x + 0.5f);
-        const float d = x - r;
-        const float a = 0.5f - d, b = 0.5f + d;
-        w[0] = 0.5f * a * a;
-        w[1] = 0.75f - d * d;
-        w[2] = 0.5f * b * b;
+        const R r = rfloor(x + R(0.5));
+        const R d = x - r;
+        const R a = R(0.5) - d, b = R(0.5) + d;
+        w[0] = R(0.5) * a * a;
+        w[1] = R(0.75) - d * d;
+        w[2] = R(0.5) * b * b;
         return (int)r - 1;
     }
 }

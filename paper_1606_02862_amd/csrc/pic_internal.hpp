@@ -23,43 +23,62 @@ constexpr float XMAX = below((float)SX), YMAX = below((float)SY), ZMAX = below((
 // Device error flags (int32 each).
 enum Flag { FLAG_CAPACITY = 0, FLAG_MIGRATE = 1, FLAG_CFL = 2, FLAG_NONFINITE = 3, NFLAGS = 4 };
 
-struct GridView {
+// Views are templated on the real type R of particles, fields and currents:
+// float (the default path) or double (the FP64 variant of the PIC cycle).
+template <class R> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <class R>
+struct GridViewT {
     int nx, ny, nz;        // cells
     int ncx, ncy, ncz;     // supercells per axis
     int nsc;               // number of supercells
     int xcd_remap;         // 1: map blockIdx so each XCD gets a contiguous slab
-    float dx, dy, dz, dt;
-    float b0x, b0y, b0z;
-    float* E;              // 3 * N, component-major, x fastest
-    float* B;
-    float* J;
+    R dx, dy, dz, dt;
+    R b0x, b0y, b0z;
+    R* E;                  // 3 * N, component-major, x fastest
+    R* B;
+    R* J;
     int32_t* flags;
-    float4* qbuf;          // deposit queue: nsc * qcap records of 2 float4 (x0,y0,z0,qw | x1,y1,z1,-)
+    typename Vec4<R>::type* qbuf;  // deposit queue: nsc * qcap records of 2 (x0,y0,z0,qw | x1,y1,z1,-)
     int qcap;              // queue slots per supercell (>= every species' frame capacity)
 };
 
-struct SpeciesView {
-    float *x, *y, *z;       // supercell-relative positions in cells: [0,8)x[0,8)x[0,4)
-    float *ux, *uy, *uz;    // u = gamma v
-    float* w;               // macro weight
+template <class R>
+struct SpeciesViewT {
+    R *x, *y, *z;           // supercell-relative positions in cells: [0,8)x[0,8)x[0,4)
+    R *ux, *uy, *uz;        // u = gamma v
+    R* w;                   // macro weight
     uint32_t* id;
     uint8_t* zs;            // charge state, or nullptr
     int32_t* count;         // particles per supercell
     int cap;                // slots per supercell (multiple of 256)
     // arrival lists: per step parity and destination supercell, cap_in slots
-    float *ix, *iy, *iz, *iux, *iuy, *iuz, *iw;
+    R *ix, *iy, *iz, *iux, *iuy, *iuz, *iw;
     uint32_t* iid;
     uint8_t* izs;
     int32_t* in_count;      // arrivals per parity and supercell (2 * nsc)
     int32_t* holes;         // per source supercell: vacated slots
     int32_t* hole_count;
     int cap_in;
-    float charge;           // in e (per unit Z when zs != nullptr)
-    float mass;
+    R charge;               // in e (per unit Z when zs != nullptr)
+    R mass;
 };
 
+using GridView = GridViewT<float>;
+using SpeciesView = SpeciesViewT<float>;
+using GridView64 = GridViewT<double>;
+using SpeciesView64 = SpeciesViewT<double>;
+
+// Largest value below the far face of a supercell of extent s in type R.
+template <class R> __host__ __device__ constexpr R face_below(R s);
+template <> __host__ __device__ constexpr float face_below<float>(float s) { return s - s * 0x1p-24f; }
+template <> __host__ __device__ constexpr double face_below<double>(double s) { return s - s * 0x1p-53; }
+
 struct Species {
-    SpeciesView v;
+    SpeciesView v;         // FP32 frames (the default path)
+    SpeciesView64 v64;     // FP64 frames (the FP64 variant)
     pic_species_t desc;
     int64_t n_init;        // particles at t = 0
     int64_t id_offset;     // first id at t = 0
@@ -78,21 +97,29 @@ __host__ __device__ inline int sc_of_block(int b, int nsc, int remap)
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_init_species(const GridView& g, const SpeciesView& s, uint64_t seed, int species_index,
+// The PIC-cycle launchers exist for R = float and R = double.
+template <class R>
+hipError_t launch_init_species(const GridViewT<R>& g, const SpeciesViewT<R>& s, uint64_t seed, int species_index,
                                int ppc, int64_t id_offset, int pos_index, int pos_ppc, int64_t pos_id_offset,
-                               float u_th, const float drift_u[3], int layout, float weight, int z_init,
+                               double u_th, const double drift_u[3], int layout, double weight, int z_init,
                                hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+inline hipError_t launch_zero_r(float* p, int64_t n, hipStream_t st) { return launch_zero_f32(p, n, st); }
+inline hipError_t launch_zero_r(double* p, int64_t n, hipStream_t st) { return launch_zero_f64(p, n, st); }
 // vmax: upper bound of |q w| max(dx,dy,dz) / (dV dt) over the species' particles
 // apar: parity of the arrivals to absorb first (-1: none); wpar: parity the
 // leavers of this step are written to
-hipError_t launch_push(const GridView& g, const SpeciesView& s, int order, float vmax, int apar, int wpar,
+template <class R>
+hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double vmax, int apar, int wpar,
                        hipStream_t st);
-hipError_t launch_migrate(const GridView& g, const SpeciesView& s, int par, hipStream_t st);
-hipError_t launch_yee_b(const GridView& g, float coef, hipStream_t st);
-hipError_t launch_yee_e(const GridView& g, float coef, hipStream_t st);
+template <class R>
+hipError_t launch_migrate(const GridViewT<R>& g, const SpeciesViewT<R>& s, int par, hipStream_t st);
+template <class R>
+hipError_t launch_yee_b(const GridViewT<R>& g, double coef, hipStream_t st);
+template <class R>
+hipError_t launch_yee_e(const GridViewT<R>& g, double coef, hipStream_t st);
 
 // FP64 diagnostics.  partial buffers hold one entry per workgroup.
 struct DiagBuffers {
@@ -102,10 +129,16 @@ struct DiagBuffers {
     int npartial;
     double* result;    // small device result vector
 };
-hipError_t launch_field_energy(const GridView& g, const DiagBuffers& d, hipStream_t st);
-hipError_t launch_kinetic(const GridView& g, const SpeciesView& s, const DiagBuffers& d, int slot, hipStream_t st);
-hipError_t launch_rho_deposit(const GridView& g, const SpeciesView& s, int order, double* rho, hipStream_t st);
-hipError_t launch_gauss(const GridView& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st);
+template <class R>
+hipError_t launch_field_energy(const GridViewT<R>& g, const DiagBuffers& d, hipStream_t st);
+template <class R>
+hipError_t launch_kinetic(const GridViewT<R>& g, const SpeciesViewT<R>& s, const DiagBuffers& d, int slot,
+                          hipStream_t st);
+template <class R>
+hipError_t launch_rho_deposit(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double* rho,
+                              hipStream_t st);
+template <class R>
+hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st);
 
 // ---------------------------------------------------------------- ionisation
 constexpr int GL_NODES = 64;                 // Gauss-Laguerre points

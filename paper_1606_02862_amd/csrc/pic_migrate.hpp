@@ -19,15 +19,16 @@
 namespace pic {
 
 // Arrival list of supercell `sc` for step parity `par`.
-__device__ inline int64_t inbox_index(const SpeciesView& s, int nsc, int par, int sc, int k)
+template <class R>
+__device__ inline int64_t inbox_index(const SpeciesViewT<R>& s, int nsc, int par, int sc, int k)
 {
     return ((int64_t)par * nsc + sc) * s.cap_in + k;
 }
 
 // Whole-workgroup call (contains barriers).  Scratch: 3 * cap_in ints plus
 // ceil(cap_in / 32) words; counters: 3 ints.  Returns the new count.
-template <int NT>
-__device__ inline int fill_supercell(const GridView& g, const SpeciesView& s, int sc, int par, int* scratch,
+template <int NT, class R>
+__device__ inline int fill_supercell(const GridViewT<R>& g, const SpeciesViewT<R>& s, int sc, int par, int* scratch,
                                      int* counters)
 {
     int* s_hole = scratch;

@@ -28,6 +28,7 @@ def gauss_laguerre64():
 
 
 _SHAPE = {"cic": 1, "tsc": 2}
+_PRECISION = {"fp32": 0, "fp64": 1}
 
 
 def grid_struct(cfg: dict) -> A.GridT:
@@ -39,6 +40,7 @@ def grid_struct(cfg: dict) -> A.GridT:
     g.rho_bg = gc["rho_bg"]
     g.seed = gc["seed"]
     g.n_ref_cm3 = gc.get("n_ref_cm3", 1e21)
+    g.precision = _PRECISION[gc.get("precision", "fp32")]
     return g
 
 
@@ -101,6 +103,8 @@ class Pic:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.nsp = len(cfg["species"])
         self.shape = cfg["grid"]["nx"], cfg["grid"]["ny"], cfg["grid"]["nz"]
+        self.fp64 = cfg["grid"].get("precision", "fp32") == "fp64"
+        self._rt = np.float64 if self.fp64 else np.float32  # host type of momenta, weights and fields
         self._alloc = TorchAllocator(self.device) if torch_alloc else None
         self._g = grid_struct(cfg)
         self._s = species_structs(cfg)
@@ -217,32 +221,34 @@ class Pic:
     def get_particles(self, s: int) -> dict:
         n = self.count(s)
         out = {k: np.zeros(n, dtype=np.float64) for k in ("x", "y", "z")}
-        out.update({k: np.zeros(n, dtype=np.float32) for k in ("ux", "uy", "uz", "w")})
+        out.update({k: np.zeros(n, dtype=self._rt) for k in ("ux", "uy", "uz", "w")})
         out["id"] = np.zeros(n, dtype=np.int64)
         out["zstate"] = np.zeros(n, dtype=np.int32)
         v = self._view(out, n)
         v.capacity = n
-        A.check(self.lib.pic_get_particles(self.h, s, C.byref(v)), self.h)
+        get = self.lib.pic_get_particles64 if self.fp64 else self.lib.pic_get_particles
+        A.check(get(self.h, s, C.byref(v)), self.h)
         return out
 
     def set_particles(self, s: int, p: dict):
         n = len(p["x"])
         arr = {k: np.ascontiguousarray(p[k], dtype=np.float64) for k in ("x", "y", "z")}
-        arr.update({k: np.ascontiguousarray(p[k], dtype=np.float32) for k in ("ux", "uy", "uz", "w")})
+        arr.update({k: np.ascontiguousarray(p[k], dtype=self._rt) for k in ("ux", "uy", "uz", "w")})
         arr["id"] = np.ascontiguousarray(p["id"], dtype=np.int64)
         arr["zstate"] = np.ascontiguousarray(p["zstate"], dtype=np.int32) if p.get("zstate") is not None else None
         v = self._view(arr, n)
-        A.check(self.lib.pic_set_particles(self.h, s, C.byref(v)), self.h)
+        put = self.lib.pic_set_particles64 if self.fp64 else self.lib.pic_set_particles
+        A.check(put(self.h, s, C.byref(v)), self.h)
 
-    @staticmethod
-    def _view(a: dict, n: int) -> A.ParticlesViewT:
-        v = A.ParticlesViewT()
+    def _view(self, a: dict, n: int):
+        v = A.ParticlesView64T() if self.fp64 else A.ParticlesViewT()
+        ct = C.c_double if self.fp64 else C.c_float
         v.count = n
         v.capacity = n
         for k in ("x", "y", "z"):
             setattr(v, k, a[k].ctypes.data_as(C.POINTER(C.c_double)))
         for k in ("ux", "uy", "uz", "w"):
-            setattr(v, k, a[k].ctypes.data_as(C.POINTER(C.c_float)))
+            setattr(v, k, a[k].ctypes.data_as(C.POINTER(ct)))
         v.id = a["id"].ctypes.data_as(C.POINTER(C.c_int64))
         if a.get("zstate") is not None:
             v.zstate = a["zstate"].ctypes.data_as(C.POINTER(C.c_int32))
@@ -250,13 +256,15 @@ class Pic:
 
     def get_fields(self):
         nx, ny, nz = self.shape
-        E, B, J = (np.zeros((3, nz, ny, nx), dtype=np.float32) for _ in range(3))
-        A.check(self.lib.pic_get_fields(self.h, E.ctypes.data, B.ctypes.data, J.ctypes.data), self.h)
+        E, B, J = (np.zeros((3, nz, ny, nx), dtype=self._rt) for _ in range(3))
+        get = self.lib.pic_get_fields64 if self.fp64 else self.lib.pic_get_fields
+        A.check(get(self.h, E.ctypes.data, B.ctypes.data, J.ctypes.data), self.h)
         return E, B, J
 
     def set_fields(self, E=None, B=None, J=None):
         nx, ny, nz = self.shape
-        conv = [None if f is None else np.ascontiguousarray(np.asarray(f, dtype=np.float32).reshape(3, nz, ny, nx))
+        conv = [None if f is None else np.ascontiguousarray(np.asarray(f, dtype=self._rt).reshape(3, nz, ny, nx))
                 for f in (E, B, J)]
         ptrs = [None if f is None else f.ctypes.data for f in conv]
-        A.check(self.lib.pic_set_fields(self.h, *ptrs), self.h)
+        put = self.lib.pic_set_fields64 if self.fp64 else self.lib.pic_set_fields
+        A.check(put(self.h, *ptrs), self.h)

@@ -81,11 +81,21 @@ def test_init_rejects_bad_shape_and_species_count(A):
     assert rc == A.PIC_ERR_ARG and "n_species" in msg
 
 
+def test_init_rejects_bad_precision_and_fp64_ionisation(A):
+    rc, _, msg = _init(A, workloads.config(0), mutate=lambda g, s: setattr(g, "precision", 2))
+    assert rc == A.PIC_ERR_ARG and "precision" in msg
+    # the FP64 variant covers the PIC cycle; ionisation stays FP32
+    cfg = workloads.reduced(3, 8, 8, 4)
+    cfg["grid"]["precision"] = "fp64"
+    rc, _, msg = _init(A, cfg)
+    assert rc == A.PIC_ERR_ARG and "FP32" in msg
+
+
 def test_null_handles(A):
     lib = A.load()
     assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
     assert lib.pic_destroy(None) == A.PIC_OK
-    assert lib.pic_abi_version() == 1
+    assert lib.pic_abi_version() == 2
     m = A.MomentsT()
     assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
 

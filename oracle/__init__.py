@@ -126,7 +126,7 @@ def make_grid(nx, ny, nz, order, dx=1.0, dy=1.0, dz=1.0, dt=0.5, b0=(0.0, 0.0, 0
 
 def grid_from_config(cfg: dict) -> Grid:
     gc = cfg["grid"]
-    order = {"cic": 1, "tsc": 2}[gc["shape"]]
+    order = {"cic": 1, "tsc": 2, "pcs": 3}[gc["shape"]]
     return make_grid(gc["nx"], gc["ny"], gc["nz"], order, gc["dx"], gc["dy"], gc["dz"], gc["dt"],
                      gc["b0"], gc["rho_bg"])
 

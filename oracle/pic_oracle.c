@@ -10,7 +10,8 @@
  * field solver, separable ("trilinear") interpolation in field gathering,
  * 3D3V, and quadratic-spline (TSC) particle shape.  It prints no formula, so
  * every routine below is the textbook definition of the named method:
- *   - CIC / TSC assignment functions (Hockney & Eastwood, cited there),
+ *   - CIC / TSC assignment functions (Hockney & Eastwood, cited there), and
+ *     the cubic B-spline (PCS) of the same family as a further shape,
  *   - relativistic Boris rotation (Boris 1970; Birdsall & Langdon),
  *   - Esirkepov charge-conserving current (Comput. Phys. Commun. 135, 2001),
  *   - Yee staggered-grid FDTD (IEEE Trans. Antennas Propag. 14, 1966),
@@ -32,7 +33,7 @@
 #include <string.h>
 
 typedef struct {
-    int32_t nx, ny, nz, order; /* order 1 = CIC, 2 = TSC */
+    int32_t nx, ny, nz, order; /* order 1 = CIC, 2 = TSC, 3 = PCS */
     double dx, dy, dz, dt;
     double b0[3];   /* uniform background B, added at gather time only */
     double rho_bg;  /* immobile neutralising background charge density */
@@ -97,6 +98,11 @@ double orc_shape(int order, double d)
 {
     double a = fabs(d);
     if (order == 1) return a < 1.0 ? 1.0 - a : 0.0;
+    if (order == 3) {  /* cubic B-spline (PCS) */
+        if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+        if (a < 2.0) { double t = 2.0 - a; return t * t * t / 6.0; }
+        return 0.0;
+    }
     if (a <= 0.5) return 0.75 - a * a;
     if (a < 1.5) { double t = 1.5 - a; return 0.5 * t * t; }
     return 0.0;
@@ -196,7 +202,9 @@ void orc_boris(int64_t n, const double* qm, double dt, const double* Ep, const d
  * qw = charge * weight of the macro-particle. */
 static int first_node(int order, double x)
 {
-    return order == 1 ? (int)floor(x) : (int)floor(x + 0.5) - 1;
+    if (order == 1) return (int)floor(x);
+    if (order == 3) return (int)floor(x) - 1;
+    return (int)floor(x + 0.5) - 1;
 }
 
 static void esirkepov1(const orc_grid* g, double qw, const double x0[3], const double x1[3], double* J)
@@ -206,7 +214,7 @@ static void esirkepov1(const orc_grid* g, double qw, const double x0[3], const d
     const double dV = g->dx * g->dy * g->dz;
     const int64_t N = ncell(g);
     int m[3];
-    double S0[3][4], DS[3][4];
+    double S0[3][5], DS[3][5];
     for (int d = 0; d < 3; ++d) {
         int f0 = first_node(g->order, x0[d]), f1 = first_node(g->order, x1[d]);
         m[d] = f0 < f1 ? f0 : f1;

@@ -51,7 +51,7 @@ def test_u01_open_interval():
 # ---------------------------------------------------------------------------
 # Assignment functions.
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_shape_partition_and_moments(order):
     xs = workloads.rng(1).uniform(-3, 3, 400)
     for x in xs:
@@ -59,8 +59,13 @@ def test_shape_partition_and_moments(order):
         s = np.array([oracle.shape(order, x - i) for i in nodes])
         assert abs(s.sum() - 1.0) < 1e-15
         assert abs((nodes * s).sum() - x) < 1e-13
-        if order == 2:  # the quadratic B-spline's variance is 1/4 at every x
+        # the B-spline of n unit boxes has discrete variance n/12 at every x
+        # from n = 3 on (quadratic 1/4, cubic 1/3); the cubic's odd moments vanish
+        if order == 2:
             assert abs(((nodes - x) ** 2 * s).sum() - 0.25) < 1e-13
+        if order == 3:
+            assert abs(((nodes - x) ** 2 * s).sum() - 1.0 / 3.0) < 1e-13
+            assert abs(((nodes - x) ** 3 * s).sum()) < 1e-13
 
 
 def test_shape_values():
@@ -69,6 +74,11 @@ def test_shape_values():
     assert oracle.shape(2, 1.0) == 0.125 and oracle.shape(2, 1.5) == 0.0 and oracle.shape(2, 2.0) == 0.0
     # continuity of the two TSC pieces at |d| = 1/2 from either side
     assert abs(oracle.shape(2, 0.5 - 1e-12) - oracle.shape(2, 0.5 + 1e-12)) < 1e-11
+    # cubic B-spline: 2/3 and 1/6 at the integers, 23/48 and 1/48 at the half integers
+    assert abs(oracle.shape(3, 0.0) - 2 / 3) < 1e-16 and abs(oracle.shape(3, 1.0) - 1 / 6) < 1e-16
+    assert oracle.shape(3, 2.0) == 0.0 and oracle.shape(3, -2.5) == 0.0
+    assert abs(oracle.shape(3, 0.5) - 23 / 48) < 1e-16 and abs(oracle.shape(3, -1.5) - 1 / 48) < 1e-16
+    assert abs(oracle.shape(3, 1.0 - 1e-12) - oracle.shape(3, 1.0 + 1e-12)) < 1e-11
 
 
 # ---------------------------------------------------------------------------
@@ -95,7 +105,7 @@ def _brute_interp(order, F, pos, off):
     return acc
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_gather_brute_force_5cube(order):
     g = oracle.make_grid(5, 5, 5, order, b0=(0.01, -0.02, 0.1))
     E, B = workloads.random_fields(7 + order, 5, 5, 5, amp=1.0)
@@ -108,7 +118,7 @@ def test_gather_brute_force_5cube(order):
             assert abs(Bp[p, c] - _brute_interp(order, B[c], pts[p], _OFF_B[c]) - g.b0[c]) < 1e-14
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_gather_uniform_and_linear_fields_exact(order):
     n = 12
     g = oracle.make_grid(n, n, n, order)
@@ -233,7 +243,7 @@ def _random_moves(seed, n, L, maxd):
     return p0, p0 + d
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 @pytest.mark.parametrize("dx", [(1.0, 1.0, 1.0), (0.7, 1.3, 0.9)])
 def test_esirkepov_continuity_residual(order, dx):
     """div J + (rho1 - rho0)/dt = 0 at every node, to round-off."""
@@ -249,7 +259,7 @@ def test_esirkepov_continuity_residual(order, dx):
     assert np.max(np.abs(res)) < 1e-14 * scale * 10
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_esirkepov_total_current_and_support(order):
     """sum J_d dV = q w (x1_d - x0_d) dx_d / dt; J vanishes off the window."""
     n = 10
@@ -280,15 +290,29 @@ def _cic_cdf(s):
     return 1.0
 
 
-@pytest.mark.parametrize("order", [1, 2])
+def _tsc_cdf(s):
+    """Integral of the quadratic B-spline from -inf to s (piecewise cubic)."""
+    if s <= -1.5:
+        return 0.0
+    if s <= -0.5:
+        return (s + 1.5) ** 3 / 6
+    if s <= 0.5:
+        return 1 / 6 + 0.75 * (s + 0.5) - (s**3 + 0.125) / 3
+    if s < 1.5:
+        return 1 - (1.5 - s) ** 3 / 6
+    return 1.0
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_esirkepov_one_axis_reduces_to_1d_flux(order):
     """Motion along x only: J_x through face i+1/2 is the charge that crossed
     it.  For CIC that is the charge times (x1 - x0) inside one cell; for TSC it
-    is the difference of the triangle's cumulative at x - (i + 1/2)."""
+    is the difference of the triangle's cumulative at x - (i + 1/2); for PCS
+    that of the quadratic B-spline's cumulative."""
     n = 12
     g = oracle.make_grid(n, n, n, order, dt=0.5)
     qw = 0.3
-    cases = [(5.2, 5.6), (5.7, 6.4), (6.1, 5.3)] if order == 2 else [(5.2, 5.6), (5.45, 5.05)]
+    cases = [(5.2, 5.6), (5.7, 6.4), (6.1, 5.3)] if order >= 2 else [(5.2, 5.6), (5.45, 5.05)]
     for x0, x1 in cases:
         y, z = 4.3, 7.8
         J = oracle.esirkepov(g, qw, x0, y, z, x1, y, z)
@@ -299,8 +323,10 @@ def test_esirkepov_one_axis_reduces_to_1d_flux(order):
                 for i in range(n):
                     if order == 1:
                         flux = (x1 - x0) if i == math.floor(x0) else 0.0
-                    else:
+                    elif order == 2:
                         flux = _cic_cdf(x1 - i - 0.5) - _cic_cdf(x0 - i - 0.5)
+                    else:
+                        flux = _tsc_cdf(x1 - i - 0.5) - _tsc_cdf(x0 - i - 0.5)
                     want = qw / g.dt * flux * sy * sz
                     assert abs(J[0, k, j, i] - want) < 1e-15
         assert np.all(J[1] == 0) and np.all(J[2] == 0)
@@ -335,9 +361,8 @@ def _brute_esirkepov(order, n, dt, qw, p0, p1):
     return J
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_esirkepov_brute_force_two_particles_5cube(order):
-    n = 5
+@pytest.mark.parametrize("order,n", [(1, 5), (2, 5), (3, 7)])
+def test_esirkepov_brute_force_two_particles(order, n):
     g = oracle.make_grid(n, n, n, order, dt=0.5)
     p0, p1 = _random_moves(21 + order, 2, n, 0.9)
     qw = np.array([-0.125, 0.25])

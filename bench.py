@@ -213,7 +213,7 @@ def main(argv=None):
     es = 8 if args.fp64 else 4
     gc = cfg["grid"]
     ncell = gc["nx"] * gc["ny"] * gc["nz"]
-    order = {"cic": 1, "tsc": 2}[gc["shape"]]
+    order = {"cic": 1, "tsc": 2, "pcs": 3}[gc["shape"]]
     n_particles = sum(ncell * s["ppc"] for s in cfg["species"] if s["mobile"])
 
     pic = P.Pic(cfg)

@@ -65,7 +65,9 @@ enum pic_status {
     PIC_ERR_STATE = -7      /* call not valid in the handle's current state */
 };
 
-typedef enum { PIC_SHAPE_CIC = 1, PIC_SHAPE_TSC = 2 } pic_shape_t;
+/* Particle shape: the B-spline assignment functions of order 1 (CIC), 2 (TSC)
+ * and 3 (PCS), used for both the field gather and the Esirkepov deposit. */
+typedef enum { PIC_SHAPE_CIC = 1, PIC_SHAPE_TSC = 2, PIC_SHAPE_PCS = 3 } pic_shape_t;
 typedef enum { PIC_LAYOUT_UNIFORM = 0, PIC_LAYOUT_SHEAR = 1, PIC_LAYOUT_BEAMS = 2 } pic_layout_t;
 typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1 } pic_rate_mode_t;
 /* Real type of particles, fields and currents on the device.  FP64 is the

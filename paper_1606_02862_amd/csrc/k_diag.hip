@@ -143,13 +143,19 @@ __device__ inline void rho_weights(double x, int* first, double* w)
         *first = (int)f;
         w[0] = 1.0 - d;
         w[1] = d;
-        w[2] = 0.0;
-    } else {
+    } else if constexpr (ORDER == 2) {
         const double r = floor(x + 0.5), d = x - r;
         *first = (int)r - 1;
         w[0] = 0.5 * (0.5 - d) * (0.5 - d);
         w[1] = 0.75 - d * d;
         w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    } else {
+        const double f = floor(x), d = x - f, e = 1.0 - d;
+        *first = (int)f - 1;
+        w[0] = e * e * e / 6.0;
+        w[1] = 2.0 / 3.0 - d * d * (1.0 - 0.5 * d);
+        w[2] = 2.0 / 3.0 - e * e * (1.0 - 0.5 * e);
+        w[3] = d * d * d / 6.0;
     }
 }
 
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_rho(GridViewT<R> g, SpeciesViewT<R> s
         if (s.zs) q *= (double)s.zs[p];
         const double qw = q * (double)s.w[p] * inv_dv;
         int fx, fy, fz;
-        double wx[3], wy[3], wz[3];
+        double wx[4], wy[4], wz[4];
         rho_weights<ORDER>((double)s.x[p], &fx, wx);
         rho_weights<ORDER>((double)s.y[p], &fy, wy);
         rho_weights<ORDER>((double)s.z[p], &fz, wz);
@@ -192,7 +198,8 @@ hipError_t launch_rho_deposit(const GridViewT<R>& g, const SpeciesViewT<R>& s, i
                               hipStream_t st)
 {
     if (order == 1) hipLaunchKernelGGL((k_rho<1, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
-    else hipLaunchKernelGGL((k_rho<2, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    else if (order == 2) hipLaunchKernelGGL((k_rho<2, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
+    else hipLaunchKernelGGL((k_rho<3, R>), dim3(g.nsc), dim3(BLOCK), 0, st, g, s, rho);
     return hipGetLastError();
 }
 

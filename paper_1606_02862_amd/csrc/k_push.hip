@@ -38,7 +38,9 @@ namespace pic {
 
 template <int ORDER, class R = float>
 struct Tile {
-    // gather tile: nodes [-1, S + ORDER] per axis
+    // gather tile: nodes [-GL, S + ORDER - GL] per axis (the staggered first
+    // node reaches -1 for CIC and TSC and -2 for PCS)
+    static constexpr int GL = (ORDER + 1) / 2;
     static constexpr int GX = SX + 1 + ORDER, GY = SY + 1 + ORDER, GZ = SZ + 1 + ORDER;
     static constexpr int GN = GX * GY * GZ;
     // current tile: nodes [-ORDER, S + ORDER] per axis
@@ -59,6 +61,7 @@ __host__ __device__ constexpr int max_cap_in(int order)
 }
 static_assert(3 * 2048 + 64 <= Tile<1>::SMEM / 4, "CIC scratch");
 static_assert(3 * 4096 + 128 <= Tile<2>::SMEM / 4, "TSC scratch");
+static_assert(3 * 4096 + 128 <= Tile<3>::SMEM / 4, "PCS scratch");
 
 // Current-tile accumulator: 64-bit fixed point for FP32, FP64 for FP64.
 template <class R>
@@ -220,7 +223,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     // ---- stage E, B with guards; zero the current tile
     for (int t = tid; t < T::GN; t += NT) {
         const int tx = t % T::GX, ty = (t / T::GX) % T::GY, tz = t / (T::GX * T::GY);
-        int gx = ox + tx - 1, gy = oy + ty - 1, gz = oz + tz - 1;
+        int gx = ox + tx - T::GL, gy = oy + ty - T::GL, gz = oz + tz - T::GL;
         gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
         gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
         gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
@@ -290,8 +293,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<ORDER>(y0 - R(0.5), wsy);
         const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<ORDER>(z0 - R(0.5), wsz);
         // tile index of the node-centred first node; the staggered components
-        // differ from it by one node at most per axis (the guard offset is 1)
-        const int bn = ((inz + 1) * T::GY + (iny + 1)) * T::GX + (inx + 1);
+        // differ from it by one node at most per axis
+        const int bn = ((inz + T::GL) * T::GY + (iny + T::GL)) * T::GX + (inx + T::GL);
         const int ox_ = isx - inx, oy_ = (isy - iny) * T::GX, oz_ = (isz - inz) * (T::GX * T::GY);
         const R Ex = interp<ORDER>(&fE[0][bn + ox_], wsx, wny, wnz);
         const R Ey = interp<ORDER>(&fE[1][bn + oy_], wnx, wsy, wnz);
@@ -474,9 +477,12 @@ hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int orde
     if (order == 1) {
         if (hz) hipLaunchKernelGGL((k_push<1, true, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
         else hipLaunchKernelGGL((k_push<1, false, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
-    } else {
+    } else if (order == 2) {
         if (hz) hipLaunchKernelGGL((k_push<2, true, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
         else hipLaunchKernelGGL((k_push<2, false, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
+    } else {
+        if (hz) hipLaunchKernelGGL((k_push<3, true, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<3, false, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
     }
     return hipGetLastError();
 }

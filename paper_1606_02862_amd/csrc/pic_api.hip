@@ -142,7 +142,8 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(g->b0[d])) return fail(nullptr, PIC_ERR_ARG, "b0 must be finite");
     if (!std::isfinite(g->rho_bg)) return fail(nullptr, PIC_ERR_ARG, "rho_bg must be finite");
-    if (shape != PIC_SHAPE_CIC && shape != PIC_SHAPE_TSC) return fail(nullptr, PIC_ERR_ARG, "unknown shape %d", (int)shape);
+    if (shape != PIC_SHAPE_CIC && shape != PIC_SHAPE_TSC && shape != PIC_SHAPE_PCS)
+        return fail(nullptr, PIC_ERR_ARG, "unknown shape %d", (int)shape);
     if (g->precision != PIC_PRECISION_FP32 && g->precision != PIC_PRECISION_FP64)
         return fail(nullptr, PIC_ERR_ARG, "unknown precision %d", (int)g->precision);
     if (n < 1 || n > PIC_MAX_SPECIES) return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..%d", PIC_MAX_SPECIES);

@@ -73,16 +73,19 @@ __device__ inline double4 make4(double a, double b, double c, double d) { return
 // CIC: nodes f, f+1 with f = floor(x); weights 1-d, d (d = x - f).
 // TSC: nodes r-1, r, r+1 with r = floor(x + 1/2); d = x - r in [-1/2, 1/2):
 //      1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2.
+// PCS (cubic B-spline): nodes f-1 .. f+2 with f = floor(x), d = x - f, e = 1 - d:
+//      e^3/6, 2/3 - d^2 (1 - d/2), 2/3 - e^2 (1 - e/2), d^3/6.
 template <int ORDER, class R>
 __device__ inline int shape_weights(R x, R* w)
 {
+    static_assert(ORDER >= 1 && ORDER <= 3, "CIC, TSC or PCS");
     if constexpr (ORDER == 1) {
         const R f = rfloor(x);
         const R d = x - f;
         w[0] = R(1) - d;
         w[1] = d;
         return (int)f;
-    } else {
+    } else if constexpr (ORDER == 2) {
         const R r = rfloor(x + R(0.5));
         const R d = x - r;
         const R a = R(0.5) - d, b = R(0.5) + d;
@@ -90,6 +93,15 @@ __device__ inline int shape_weights(R x, R* w)
         w[1] = R(0.75) - d * d;
         w[2] = R(0.5) * b * b;
         return (int)r - 1;
+    } else {
+        const R f = rfloor(x);
+        const R d = x - f, e = R(1) - d;
+        const R sixth = R(1) / R(6), two3 = R(2) / R(3);
+        w[0] = sixth * e * e * e;
+        w[1] = two3 - d * d * (R(1) - R(0.5) * d);
+        w[2] = two3 - e * e * (R(1) - R(0.5) * e);
+        w[3] = sixth * d * d * d;
+        return (int)f - 1;
     }
 }
 

@@ -27,7 +27,7 @@ def gauss_laguerre64():
     return x, w
 
 
-_SHAPE = {"cic": 1, "tsc": 2}
+_SHAPE = {"cic": 1, "tsc": 2, "pcs": 3}
 _PRECISION = {"fp32": 0, "fp64": 1}
 
 

@@ -47,7 +47,7 @@ def _init(A, cfg, shape=None, nsp=None, mutate=None):
     if mutate:
         mutate(g, s)
     h = C.c_void_p(123)
-    shp = shape if shape is not None else {"cic": 1, "tsc": 2}[cfg["grid"]["shape"]]
+    shp = shape if shape is not None else {"cic": 1, "tsc": 2, "pcs": 3}[cfg["grid"]["shape"]]
     rc = A.load().pic_init(C.byref(h), C.byref(g), s, len(cfg["species"]) if nsp is None else nsp, shp, None, None)
     return rc, h, A.load().pic_last_error(None).decode()
 
@@ -75,7 +75,7 @@ def test_init_rejects_bad_arguments(A, what, mutate, needle):
 
 
 def test_init_rejects_bad_shape_and_species_count(A):
-    rc, _, msg = _init(A, workloads.config(0), shape=3)
+    rc, _, msg = _init(A, workloads.config(0), shape=4)
     assert rc == A.PIC_ERR_ARG and "shape" in msg
     rc, _, msg = _init(A, workloads.config(0), nsp=0)
     assert rc == A.PIC_ERR_ARG and "n_species" in msg

@@ -86,6 +86,51 @@ def test_one_step_parity(P, idx, box, warm):
     assert err["E"] <= 1e-4 and err["B"] <= 1e-4
 
 
+@pytest.mark.parametrize("idx,box,warm", [
+    (0, (16, 16, 16), 10),       # PCS electrons, immobile background
+    (2, (16, 16, 8), 10),        # PCS electrons + protons in B0
+])
+def test_one_step_parity_pcs(P, idx, box, warm):
+    """The cubic B-spline (PCS) shape: 4-node gather, 5-node Esirkepov window,
+    a 2-node low guard in the staged field tile."""
+    cfg = workloads.config(idx, nx=box[0], ny=box[1], nz=box[2], shape="pcs")
+    _print("one-step parity PCS", idx, box)
+    st = _s0(cfg, warm)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print(err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-5
+    assert err["J"] <= 1e-4
+    assert max(err["x"]) <= 2e-6
+    assert err["E"] <= 1e-4 and err["B"] <= 1e-4
+
+
+def test_energy_trace_100_steps_pcs(P):
+    cfg = workloads.config(0, shape="pcs")
+    nsteps = 100
+    st = oracle.init_state(cfg)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        ref = s0.copy()
+        tr = oracle.step(ref, nsteps, trace=True)
+        t_ref = oracle.energy_trace_total(tr)
+        ms = []
+        for _ in range(nsteps + 1):
+            ms.append(pic.moments())
+            if len(ms) <= nsteps:
+                pic.step(1)
+    we = np.array([m["w_e"] for m in ms])
+    wb = np.array([m["w_b"] for m in ms])
+    k = np.array([m["kinetic_total"] for m in ms])
+    t_gpu = we[:-1] + wb[:-1] + 0.5 * (k[:-1] + k[1:])
+    rel = np.abs(t_gpu - t_ref) / t_ref
+    _print("PCS trace max rel", rel.max(), "gauss", ms[-1]["gauss_max"], "rho_max", ms[-1]["rho_max"])
+    assert rel.max() <= 1e-3
+    assert ms[-1]["gauss_max"] <= 1e-4 * ms[-1]["rho_max"]
+
+
 def test_one_step_parity_single_supercell_wraps_onto_itself(P):
     """An 8x8x4 box is one supercell: every guard and every mover wraps to itself."""
     cfg = workloads.reduced(2, 8, 8, 4)

@@ -47,7 +47,7 @@ def lib():
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("order", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
-                ("b0", C.c_double * 3), ("rho_bg", C.c_double)]
+                ("b0", C.c_double * 3), ("rho_bg", C.c_double), ("gather", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Particles(C.Structure):
@@ -115,12 +115,14 @@ def shape(order: int, d: float) -> float:
     return lib().orc_shape(order, float(d))
 
 
-def make_grid(nx, ny, nz, order, dx=1.0, dy=1.0, dz=1.0, dt=0.5, b0=(0.0, 0.0, 0.0), rho_bg=0.0) -> Grid:
+def make_grid(nx, ny, nz, order, dx=1.0, dy=1.0, dz=1.0, dt=0.5, b0=(0.0, 0.0, 0.0), rho_bg=0.0,
+              galerkin=False) -> Grid:
     g = Grid()
     g.nx, g.ny, g.nz, g.order = nx, ny, nz, order
     g.dx, g.dy, g.dz, g.dt = dx, dy, dz, dt
     g.b0[:] = list(b0)
     g.rho_bg = rho_bg
+    g.gather = 1 if galerkin else 0
     return g
 
 
@@ -128,7 +130,7 @@ def grid_from_config(cfg: dict) -> Grid:
     gc = cfg["grid"]
     order = {"cic": 1, "tsc": 2, "pcs": 3}[gc["shape"]]
     return make_grid(gc["nx"], gc["ny"], gc["nz"], order, gc["dx"], gc["dy"], gc["dz"], gc["dt"],
-                     gc["b0"], gc["rho_bg"])
+                     gc["b0"], gc["rho_bg"], galerkin=gc.get("gather", "standard") == "galerkin")
 
 
 def zero_fields(g: Grid) -> np.ndarray:

@@ -37,6 +37,9 @@ typedef struct {
     double dx, dy, dz, dt;
     double b0[3];   /* uniform background B, added at gather time only */
     double rho_bg;  /* immobile neutralising background charge density */
+    int32_t gather; /* 0: every axis with the shape's order; 1: Galerkin, one
+                       order lower along each of a component's staggered axes */
+    int32_t pad;
 } orc_grid;
 
 typedef struct {
@@ -97,6 +100,7 @@ static void draw4(uint64_t seed, uint64_t id, uint64_t species, uint64_t purpose
 double orc_shape(int order, double d)
 {
     double a = fabs(d);
+    if (order == 0) return (d >= -0.5 && d < 0.5) ? 1.0 : 0.0; /* NGP; a tie goes to the upper node */
     if (order == 1) return a < 1.0 ? 1.0 - a : 0.0;
     if (order == 3) {  /* cubic B-spline (PCS) */
         if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
@@ -125,21 +129,26 @@ static inline int64_t ncell(const orc_grid* g)
 }
 
 /* Field interpolation at one point: sum over all nodes in reach of the
- * shape, weight Sx*Sy*Sz, with the component's own half-cell offsets. */
+ * shape, weight Sx*Sy*Sz, with the component's own half-cell offsets.  In
+ * the Galerkin gather an axis along which the component is staggered uses
+ * the shape one order lower. */
 static double interp(const orc_grid* g, const double* f, double x, double y, double z,
                      double ox, double oy, double oz)
 {
     double px = x - ox, py = y - oy, pz = z - oz;
     int64_t bx = (int64_t)floor(px), by = (int64_t)floor(py), bz = (int64_t)floor(pz);
+    const int qx = (g->gather && ox != 0.0) ? g->order - 1 : g->order;
+    const int qy = (g->gather && oy != 0.0) ? g->order - 1 : g->order;
+    const int qz = (g->gather && oz != 0.0) ? g->order - 1 : g->order;
     double acc = 0.0;
     for (int64_t k = bz - 2; k <= bz + 3; ++k) {
-        double sz = orc_shape(g->order, pz - (double)k);
+        double sz = orc_shape(qz, pz - (double)k);
         if (sz == 0.0) continue;
         for (int64_t j = by - 2; j <= by + 3; ++j) {
-            double sy = orc_shape(g->order, py - (double)j);
+            double sy = orc_shape(qy, py - (double)j);
             if (sy == 0.0) continue;
             for (int64_t i = bx - 2; i <= bx + 3; ++i) {
-                double sx = orc_shape(g->order, px - (double)i);
+                double sx = orc_shape(qx, px - (double)i);
                 if (sx == 0.0) continue;
                 acc += sx * sy * sz * f[gidx(g, i, j, k)];
             }

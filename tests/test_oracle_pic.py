@@ -141,6 +141,75 @@ def test_gather_uniform_and_linear_fields_exact(order):
 
 
 # ---------------------------------------------------------------------------
+# Galerkin gather: one order lower along a component's staggered axes.
+
+def test_ngp_shape_order0():
+    """Order 0 (nearest grid point) on the half-integer grid: weight 1 on the
+    node within [-1/2, 1/2), the upper node taking a tie."""
+    assert oracle.shape(0, 0.0) == 1.0 and oracle.shape(0, -0.5) == 1.0 and oracle.shape(0, 0.5) == 0.0
+    assert oracle.shape(0, 0.49) == 1.0 and oracle.shape(0, -0.51) == 0.0
+    for x in workloads.rng(5).uniform(-3, 3, 200):
+        nodes = np.arange(math.floor(x) - 2, math.floor(x) + 3)
+        assert sum(oracle.shape(0, x - i) for i in nodes) == 1.0
+
+
+def _brute_interp_orders(orders, F, pos, off):
+    nz, ny, nx = F.shape
+    acc = 0.0
+    for k in range(nz):
+        sz = oracle.shape(orders[2], _min_image(pos[2] - off[2] - k, nz))
+        for j in range(ny):
+            sy = oracle.shape(orders[1], _min_image(pos[1] - off[1] - j, ny))
+            for i in range(nx):
+                sx = oracle.shape(orders[0], _min_image(pos[0] - off[0] - i, nx))
+                acc += sx * sy * sz * F[k, j, i]
+    return acc
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_galerkin_gather_brute_force_5cube(order):
+    g = oracle.make_grid(5, 5, 5, order, b0=(0.01, -0.02, 0.1), galerkin=True)
+    E, B = workloads.random_fields(17 + order, 5, 5, 5, amp=1.0)
+    pts = workloads.rng(13 + order).uniform(0, 5, size=(3, 3))
+    Ep, Bp = oracle.gather(g, E, B, pts[:, 0], pts[:, 1], pts[:, 2])
+    for p in range(3):
+        for c in range(3):
+            oe = [order - 1 if o else order for o in _OFF_E[c]]
+            ob = [order - 1 if o else order for o in _OFF_B[c]]
+            assert abs(Ep[p, c] - _brute_interp_orders(oe, E[c], pts[p], _OFF_E[c])) < 1e-14
+            assert abs(Bp[p, c] - _brute_interp_orders(ob, B[c], pts[p], _OFF_B[c]) - g.b0[c]) < 1e-14
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_galerkin_equals_standard_for_fields_uniform_along_staggered_axes(order):
+    """Every shape sums to one, so a component that does not vary along its
+    staggered axes is gathered identically by both schemes."""
+    n = 10
+    g0 = oracle.make_grid(n, n, n, order)
+    g1 = oracle.make_grid(n, n, n, order, galerkin=True)
+    r = workloads.rng(31)
+    E = np.zeros((3, n, n, n))
+    B = np.zeros((3, n, n, n))
+    for c in range(3):
+        base = r.uniform(-1, 1, (n, n, n))
+        # E_c varies only across axis c; B_c only along axis c
+        e = base.mean(axis=2 - c, keepdims=True)
+        E[c] = np.broadcast_to(e, (n, n, n))
+        keep = [ax for ax in (0, 1, 2) if ax != 2 - c]
+        b = base.mean(axis=tuple(keep), keepdims=True)
+        B[c] = np.broadcast_to(b, (n, n, n))
+    pts = r.uniform(0, n, size=(40, 3))
+    E0, B0 = oracle.gather(g0, E, B, *pts.T)
+    E1, B1 = oracle.gather(g1, E, B, *pts.T)
+    assert np.max(np.abs(E0 - E1)) < 1e-14 and np.max(np.abs(B0 - B1)) < 1e-14
+    # and they differ for a generic field
+    E2, B2 = workloads.random_fields(32, n, n, n, amp=1.0)
+    Ea, _ = oracle.gather(g0, E2, B2, *pts.T)
+    Eb, _ = oracle.gather(g1, E2, B2, *pts.T)
+    assert np.max(np.abs(Ea - Eb)) > 1e-3
+
+
+# ---------------------------------------------------------------------------
 # Boris push.
 
 def _circumcenter(p0, p1, p2):

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 2
+#define PIC_ABI_VERSION 3
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
 #define PIC_SUPERCELL_X 8
@@ -76,6 +76,11 @@ typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1 } pic_rate_mode_t;
  * double, with the current tile accumulated by native FP64 LDS atomics and
  * flushed by FP64 global atomics.  Ionisation needs FP32. */
 typedef enum { PIC_PRECISION_FP32 = 0, PIC_PRECISION_FP64 = 1 } pic_precision_t;
+/* Field gather: STANDARD interpolates every component with the particle's
+ * shape on all three axes at its own Yee location; GALERKIN uses the shape
+ * one order lower along each axis on which the component is staggered
+ * (E_d along d, B_d along the two others; order 0 is the nearest node). */
+typedef enum { PIC_GATHER_STANDARD = 0, PIC_GATHER_GALERKIN = 1 } pic_gather_t;
 
 /* Periodic grid.  nx, ny, nz must be positive multiples of 8, 8, 4 (the
  * supercell).  dt must satisfy the 3D Courant limit
@@ -89,6 +94,8 @@ typedef struct {
     double rho_bg;      /* immobile neutralising background charge density (in e n0) */
     uint64_t seed;      /* Philox key for every random draw */
     double n_ref_cm3;   /* physical density of n0 = 1, used only by ionisation */
+    int32_t gather;     /* pic_gather_t (0: standard) */
+    int32_t reserved1;
 } pic_grid_t;
 
 /* One particle species.

@@ -19,7 +19,8 @@ PIC_OK, PIC_ERR_ARG, PIC_ERR_OOM, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PI
 class GridT(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
-                ("b0", C.c_double * 3), ("rho_bg", C.c_double), ("seed", C.c_uint64), ("n_ref_cm3", C.c_double)]
+                ("b0", C.c_double * 3), ("rho_bg", C.c_double), ("seed", C.c_uint64), ("n_ref_cm3", C.c_double),
+                ("gather", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class SpeciesT(C.Structure):

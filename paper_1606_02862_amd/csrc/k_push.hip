@@ -67,27 +67,34 @@ static_assert(3 * 4096 + 128 <= Tile<3>::SMEM / 4, "PCS scratch");
 template <class R>
 using JAcc = typename std::conditional<std::is_same<R, float>::value, unsigned long long, double>::type;
 
-// Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f,
-// f0 pointing at the component's first node (x fastest in the tile).
-template <int ORDER, class R>
-__device__ inline R interp(const R* f0, const R* wx, const R* wy, const R* wz)
+// Separable interpolation of one staged component: sum_c wz sum_b wy sum_a wx f
+// over PX x PY x PZ nodes, f0 pointing at the component's first node (x
+// fastest in the tile of a shape of order ORDER).
+template <int ORDER, int PX, int PY, int PZ, class R>
+__device__ inline R interp_n(const R* f0, const R* wx, const R* wy, const R* wz)
 {
     using T = Tile<ORDER>;
     R acc = R(0);
 #pragma unroll
-    for (int c = 0; c < T::NP; ++c) {
+    for (int c = 0; c < PZ; ++c) {
         R accy = R(0);
 #pragma unroll
-        for (int b = 0; b < T::NP; ++b) {
+        for (int b = 0; b < PY; ++b) {
             const R* row = f0 + (c * T::GY + b) * T::GX;
             R accx = R(0);
 #pragma unroll
-            for (int a = 0; a < T::NP; ++a) accx = rfma(wx[a], row[a], accx);
+            for (int a = 0; a < PX; ++a) accx = rfma(wx[a], row[a], accx);
             accy = rfma(wy[b], accx, accy);
         }
         acc = rfma(wz[c], accy, acc);
     }
     return acc;
+}
+template <int ORDER, class R>
+__device__ inline R interp(const R* f0, const R* wx, const R* wy, const R* wz)
+{
+    constexpr int P = ORDER + 1;
+    return interp_n<ORDER, P, P, P>(f0, wx, wy, wz);
 }
 
 // Old shape and shape change on the general window [m, m + W) of one axis.
@@ -197,7 +204,7 @@ __device__ inline const E& at(const E* base, unsigned byte_off)
 // Waves per SIMD the register budget is fitted to: 4 in FP32, 2 in FP64.
 template <class R> constexpr int push_waves() { return std::is_same<R, float>::value ? 4 : 2; }
 
-template <int ORDER, bool HAS_Z, int NT, class R>
+template <int ORDER, bool HAS_Z, bool GAL, int NT, class R>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(push_waves<R>())))
 void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int wpar)
 {
@@ -287,21 +294,25 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
             if constexpr (HAS_Z) nzs = pzs[sn];
         }
 
-        // ---- gather at node-centred and half-shifted positions per axis
-        R wnx[T::NP], wny[T::NP], wnz[T::NP], wsx[T::NP], wsy[T::NP], wsz[T::NP];
-        const int inx = shape_weights<ORDER>(x0, wnx), isx = shape_weights<ORDER>(x0 - R(0.5), wsx);
-        const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<ORDER>(y0 - R(0.5), wsy);
-        const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<ORDER>(z0 - R(0.5), wsz);
-        // tile index of the node-centred first node; the staggered components
-        // differ from it by one node at most per axis
+        // ---- gather at node-centred and half-shifted positions per axis;
+        // the Galerkin gather takes the shape one order lower (ORDER nodes)
+        // along each axis on which a component is staggered
+        constexpr int SO = GAL ? ORDER - 1 : ORDER;
+        constexpr int P = T::NP, Q = SO + 1;
+        R wnx[P], wny[P], wnz[P], wsx[P], wsy[P], wsz[P];
+        const int inx = shape_weights<ORDER>(x0, wnx), isx = shape_weights<SO>(x0 - R(0.5), wsx);
+        const int iny = shape_weights<ORDER>(y0, wny), isy = shape_weights<SO>(y0 - R(0.5), wsy);
+        const int inz = shape_weights<ORDER>(z0, wnz), isz = shape_weights<SO>(z0 - R(0.5), wsz);
+        // tile index of the node-centred first node; the staggered first nodes
+        // differ from it by one node at most per axis and lie in the tile
         const int bn = ((inz + T::GL) * T::GY + (iny + T::GL)) * T::GX + (inx + T::GL);
         const int ox_ = isx - inx, oy_ = (isy - iny) * T::GX, oz_ = (isz - inz) * (T::GX * T::GY);
-        const R Ex = interp<ORDER>(&fE[0][bn + ox_], wsx, wny, wnz);
-        const R Ey = interp<ORDER>(&fE[1][bn + oy_], wnx, wsy, wnz);
-        const R Ez = interp<ORDER>(&fE[2][bn + oz_], wnx, wny, wsz);
-        const R Bx = interp<ORDER>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
-        const R By = interp<ORDER>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
-        const R Bz = interp<ORDER>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
+        const R Ex = interp_n<ORDER, Q, P, P>(&fE[0][bn + ox_], wsx, wny, wnz);
+        const R Ey = interp_n<ORDER, P, Q, P>(&fE[1][bn + oy_], wnx, wsy, wnz);
+        const R Ez = interp_n<ORDER, P, P, Q>(&fE[2][bn + oz_], wnx, wny, wsz);
+        const R Bx = interp_n<ORDER, P, Q, Q>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
+        const R By = interp_n<ORDER, Q, P, Q>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
+        const R Bz = interp_n<ORDER, Q, Q, P>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
 
         // ---- relativistic Boris: half kick, rotation, half kick
         const R h = q * qm;
@@ -459,14 +470,27 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     }
 }
 
+template <int ORDER, int NT, class R>
+static void launch_push_order(const GridViewT<R>& g, const SpeciesViewT<R>& s, bool gal, R jscale, R jinv, int apar,
+                              int wpar, hipStream_t st)
+{
+    const dim3 grid(g.nsc), block(NT);
+    const bool hz = s.zs != nullptr;
+    if (gal) {
+        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<ORDER, false, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+    } else {
+        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+        else hipLaunchKernelGGL((k_push<ORDER, false, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+    }
+}
+
 template <class R>
-hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double vmax, int apar, int wpar,
-                       hipStream_t st)
+hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, bool galerkin, double vmax,
+                       int apar, int wpar, hipStream_t st)
 {
     if (s.cap > g.qcap) return hipErrorInvalidValue;  // the deposit queue must hold a full supercell
     if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
-    const dim3 grid(g.nsc);
-    const bool hz = s.zs != nullptr;
     R jscale = R(1), jinv = R(1);
     if constexpr (std::is_same<R, float>::value) {
         // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
@@ -474,20 +498,14 @@ hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int orde
         jscale = vf > 0.0f ? 1073741824.0f / vf : 1.0f;
         jinv = 1.0f / jscale;
     }
-    if (order == 1) {
-        if (hz) hipLaunchKernelGGL((k_push<1, true, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<1, false, 256, R>), grid, dim3(256), 0, st, g, s, jscale, jinv, apar, wpar);
-    } else if (order == 2) {
-        if (hz) hipLaunchKernelGGL((k_push<2, true, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<2, false, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
-    } else {
-        if (hz) hipLaunchKernelGGL((k_push<3, true, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<3, false, 512, R>), grid, dim3(512), 0, st, g, s, jscale, jinv, apar, wpar);
-    }
+    if (order == 1) launch_push_order<1, 256>(g, s, galerkin, jscale, jinv, apar, wpar, st);
+    else if (order == 2) launch_push_order<2, 512>(g, s, galerkin, jscale, jinv, apar, wpar, st);
+    else launch_push_order<3, 512>(g, s, galerkin, jscale, jinv, apar, wpar, st);
     return hipGetLastError();
 }
 
-template hipError_t launch_push<float>(const GridView&, const SpeciesView&, int, double, int, int, hipStream_t);
-template hipError_t launch_push<double>(const GridView64&, const SpeciesView64&, int, double, int, int, hipStream_t);
+template hipError_t launch_push<float>(const GridView&, const SpeciesView&, int, bool, double, int, int, hipStream_t);
+template hipError_t launch_push<double>(const GridView64&, const SpeciesView64&, int, bool, double, int, int,
+                                        hipStream_t);
 
 }  // namespace pic

@@ -146,6 +146,8 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
         return fail(nullptr, PIC_ERR_ARG, "unknown shape %d", (int)shape);
     if (g->precision != PIC_PRECISION_FP32 && g->precision != PIC_PRECISION_FP64)
         return fail(nullptr, PIC_ERR_ARG, "unknown precision %d", (int)g->precision);
+    if (g->gather != PIC_GATHER_STANDARD && g->gather != PIC_GATHER_GALERKIN)
+        return fail(nullptr, PIC_ERR_ARG, "unknown gather %d", (int)g->gather);
     if (n < 1 || n > PIC_MAX_SPECIES) return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..%d", PIC_MAX_SPECIES);
     double ids = 0.0;
     for (int s = 0; s < n; ++s) {
@@ -578,7 +580,8 @@ int step_t(pic_ctx* c, int n)
         const int wpar = it & 1, apar = it > 0 ? ((it - 1) & 1) : -1;
         for (int s = 0; s < c->nsp; ++s) {
             if (!c->sp[s].desc.mobile) continue;
-            HIPCHK(c, launch_push<R>(g, sview<R>(c, s), c->order, push_vmax(c, s), apar, wpar, c->stream));
+            HIPCHK(c, launch_push<R>(g, sview<R>(c, s), c->order, c->grid.gather == PIC_GATHER_GALERKIN,
+                                     push_vmax(c, s), apar, wpar, c->stream));
             c->pending_launches += c->timing ? 1 : 0;
         }
         if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));

@@ -70,6 +70,7 @@ __device__ inline float4 make4(float a, float b, float c, float d) { return make
 __device__ inline double4 make4(double a, double b, double c, double d) { return make_double4(a, b, c, d); }
 
 // ---------------------------------------------------------------- shapes
+// NGP (order 0, used by the Galerkin gather): node floor(x + 1/2), weight 1.
 // CIC: nodes f, f+1 with f = floor(x); weights 1-d, d (d = x - f).
 // TSC: nodes r-1, r, r+1 with r = floor(x + 1/2); d = x - r in [-1/2, 1/2):
 //      1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2.
@@ -78,8 +79,12 @@ __device__ inline double4 make4(double a, double b, double c, double d) { return
 template <int ORDER, class R>
 __device__ inline int shape_weights(R x, R* w)
 {
-    static_assert(ORDER >= 1 && ORDER <= 3, "CIC, TSC or PCS");
-    if constexpr (ORDER == 1) {
+    static_assert(ORDER >= 0 && ORDER <= 3, "NGP, CIC, TSC or PCS");
+    if constexpr (ORDER == 0) {
+        const R f = rfloor(x + R(0.5));  // nearest node, the upper one on a tie
+        w[0] = R(1);
+        return (int)f;
+    } else if constexpr (ORDER == 1) {
         const R f = rfloor(x);
         const R d = x - f;
         w[0] = R(1) - d;

@@ -111,9 +111,10 @@ inline hipError_t launch_zero_r(double* p, int64_t n, hipStream_t st) { return l
 // vmax: upper bound of |q w| max(dx,dy,dz) / (dV dt) over the species' particles
 // apar: parity of the arrivals to absorb first (-1: none); wpar: parity the
 // leavers of this step are written to
+// galerkin: the reduced-order gather along staggered axes (PIC_GATHER_GALERKIN)
 template <class R>
-hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double vmax, int apar, int wpar,
-                       hipStream_t st);
+hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, bool galerkin, double vmax,
+                       int apar, int wpar, hipStream_t st);
 template <class R>
 hipError_t launch_migrate(const GridViewT<R>& g, const SpeciesViewT<R>& s, int par, hipStream_t st);
 template <class R>

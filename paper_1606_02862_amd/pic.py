@@ -41,6 +41,7 @@ def grid_struct(cfg: dict) -> A.GridT:
     g.seed = gc["seed"]
     g.n_ref_cm3 = gc.get("n_ref_cm3", 1e21)
     g.precision = _PRECISION[gc.get("precision", "fp32")]
+    g.gather = {"standard": 0, "galerkin": 1}[gc.get("gather", "standard")]
     return g
 
 

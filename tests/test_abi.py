@@ -66,6 +66,7 @@ def _init(A, cfg, shape=None, nsp=None, mutate=None):
      "z_init"),
     ("ionize_into without charge states", lambda g, s: setattr(s[0], "ionize_into", 0), "ionize_into"),
     ("cap below ppc", lambda g, s: setattr(s[0], "cap_ppc", 3), "cap_ppc"),
+    ("unknown gather", lambda g, s: setattr(g, "gather", 2), "gather"),
 ])
 def test_init_rejects_bad_arguments(A, what, mutate, needle):
     rc, h, msg = _init(A, workloads.config(0), mutate=mutate)
@@ -95,7 +96,7 @@ def test_null_handles(A):
     lib = A.load()
     assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
     assert lib.pic_destroy(None) == A.PIC_OK
-    assert lib.pic_abi_version() == 2
+    assert lib.pic_abi_version() == 3
     m = A.MomentsT()
     assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
 

@@ -101,6 +101,19 @@ def test_fp64_one_step_parity_pcs(P):
     assert max(err["u"]) <= 1e-12 and max(err["x"]) <= 1e-12 and err["J"] <= 1e-12
 
 
+@pytest.mark.parametrize("shape", ["cic", "pcs"])
+def test_fp64_one_step_parity_galerkin(P, shape):
+    cfg = _fp64(workloads.config(2, nx=16, ny=16, nz=8, shape=shape, gather="galerkin"))
+    st = oracle.init_state(cfg)
+    oracle.step(st, 6)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print("fp64 Galerkin", shape, err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-12 and max(err["x"]) <= 1e-12 and err["J"] <= 1e-12
+
+
 def test_fp64_energy_trace_100_steps(P):
     cfg = _fp64(workloads.config(0))
     nsteps = cfg["steps"]

@@ -107,6 +107,66 @@ def test_one_step_parity_pcs(P, idx, box, warm):
     assert err["E"] <= 1e-4 and err["B"] <= 1e-4
 
 
+@pytest.mark.parametrize("shape", ["cic", "tsc", "pcs"])
+def test_one_step_parity_galerkin(P, shape):
+    """The Galerkin gather: each component's shape one order lower along the
+    axes on which it is staggered (nearest node for CIC), same deposit."""
+    cfg = workloads.config(2, nx=16, ny=16, nz=8, shape=shape, gather="galerkin")
+    _print("one-step parity Galerkin", shape)
+    st = _s0(cfg, 10)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print(err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-5
+    assert err["J"] <= 1e-4
+    assert max(err["x"]) <= 2e-6
+    assert err["E"] <= 1e-4 and err["B"] <= 1e-4
+
+
+def test_galerkin_gather_differs_from_standard(P):
+    """The switch reaches the kernel: one step from the same state with the two
+    gathers gives different momenta (by far more than round-off)."""
+    cfg = workloads.config(2, nx=16, ny=16, nz=8)
+    st = _s0(cfg, 10)
+    out = {}
+    for gather in ("standard", "galerkin"):
+        cfg["grid"]["gather"] = gather
+        with P.Pic(cfg) as pic:
+            parity.shared_start(pic, st)
+            pic.step(1)
+            p = pic.get_particles(0)
+            out[gather] = p["ux"][np.argsort(p["id"])]
+    du = np.max(np.abs(out["standard"] - out["galerkin"]))
+    _print("standard vs Galerkin max |dux|", du)
+    assert du > 1e-4 * np.max(np.abs(out["standard"]))
+
+
+def test_energy_trace_100_steps_galerkin_tsc(P):
+    cfg = workloads.config(0, shape="tsc", gather="galerkin")
+    nsteps = 100
+    st = oracle.init_state(cfg)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        ref = s0.copy()
+        tr = oracle.step(ref, nsteps, trace=True)
+        t_ref = oracle.energy_trace_total(tr)
+        ms = []
+        for _ in range(nsteps + 1):
+            ms.append(pic.moments())
+            if len(ms) <= nsteps:
+                pic.step(1)
+    we = np.array([m["w_e"] for m in ms])
+    wb = np.array([m["w_b"] for m in ms])
+    k = np.array([m["kinetic_total"] for m in ms])
+    t_gpu = we[:-1] + wb[:-1] + 0.5 * (k[:-1] + k[1:])
+    rel = np.abs(t_gpu - t_ref) / t_ref
+    _print("Galerkin TSC trace max rel", rel.max())
+    assert rel.max() <= 1e-3
+    assert ms[-1]["gauss_max"] <= 1e-4 * ms[-1]["rho_max"]
+
+
 def test_energy_trace_100_steps_pcs(P):
     cfg = workloads.config(0, shape="pcs")
     nsteps = 100

@@ -34,10 +34,12 @@ def features(T_eV, ne_cm3, Z):
     return X
 
 
-def ln_rate_prior(kT, ne, P, q):
-    kT, ne, P, q = (np.asarray(a, dtype=np.float64) for a in (kT, ne, P, q))
+def ln_rate_prior(kT, ne, P, q, a=LOTZ_A):
+    """The analytic prior: the outermost subshell's plain Lotz rate with
+    e^z E1(z) replaced by ln(1 + 1/z) (z = P/kT)."""
+    kT, ne, P, q, a = (np.asarray(v, dtype=np.float64) for v in (kT, ne, P, q, a))
     z = P / kT
-    return np.log(ne * vbar(kT) * LOTZ_A * q / (P * kT)) - z + np.log(np.log1p(1.0 / z))
+    return np.log(ne * vbar(kT) * a * q / (P * kT)) - z + np.log(np.log1p(1.0 / z))
 
 
 def silu(z):
@@ -88,13 +90,15 @@ def loss_and_grad(p, X, t):
     return loss, g
 
 
-def ln_rate(p, mu, s, T_eV, ne_cm3, Z, P_table, q_table):
-    """Surrogate ln nu for given inputs (FP64 evaluation of the network)."""
+def ln_rate(p, mu, s, T_eV, ne_cm3, Z, P_table, q_table, a_table=None):
+    """Surrogate ln nu for given inputs (FP64 evaluation of the network);
+    P, q, a of each state's outermost subshell (a defaults to 4.5e-14)."""
     Z = np.asarray(Z).astype(np.int64)
     P = np.asarray(P_table, dtype=np.float64)[Z]
     q = np.asarray(q_table, dtype=np.float64)[Z]
+    a = LOTZ_A if a_table is None else np.asarray(a_table, dtype=np.float64)[Z]
     y, _ = forward(p, features(T_eV, ne_cm3, Z))
-    return ln_rate_prior(T_eV, ne_cm3, P, q) + mu + s * y
+    return ln_rate_prior(T_eV, ne_cm3, P, q, a) + mu + s * y
 
 
 __all__ = ["features", "ln_rate_prior", "silu", "forward", "loss_and_grad", "init_params", "ln_rate",

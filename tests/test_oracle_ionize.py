@@ -176,3 +176,148 @@ def test_prior_residual_is_bounded_by_e1_inequalities():
     r = ionize.ln_rate_exact(T, ne, P, q) - mlp.ln_rate_prior(T, ne, P, q)
     lo = np.log(np.log1p(2 / z) / (2 * np.log1p(1 / z)))
     assert np.all(r <= 1e-12) and np.all(r >= lo - 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Subshells with Lotz's b, c terms; successive events; ionisation-energy loss.
+
+@pytest.mark.parametrize("kT,P,b,c", [(5.0, 11.3, 0.7, 0.4), (40.0, 64.5, 0.3, 2.5), (2.0, 24.4, 0.9, 0.05),
+                                      (100.0, 392.0, 0.5, 1.0)])
+def test_lotz_bc_subshell_matches_e1_closed_form(kT, P, b, c):
+    """With E = P + kT x the b-term integral is e^{c} E1(z + c) / (1 + c/z) (z = P/kT):
+    <sigma v> = vbar a q / (P kT) [E1(z) - b e^{c} E1(z + c) / (1 + c/z)]."""
+    a, q = 3.9e-14, 2.0
+    got = ionize.sigma_v_exact(kT, P, q, a, b, c)
+    z = P / kT
+    want = ionize.vbar(kT) * a * q / (P * kT) * (special.exp1(z) - b * math.exp(c) * special.exp1(z + c) / (1 + c / z))
+    assert abs(got / want - 1) < 1e-12
+    # b = 0 is the plain form whatever c is
+    assert ionize.sigma_v_exact(kT, P, q, a, 0.0, c) == pytest.approx(ionize.sigma_v_exact(kT, P, q, a), rel=1e-15)
+
+
+def test_lotz_two_subshells_direct_maxwellian_integral():
+    """sigma(E) summed over two subshells with their own thresholds and b, c,
+    integrated against the Maxwellian directly (no substitution)."""
+    shells = [(24.4, 4.0e-14, 0.6, 0.6, 1.0), (300.0, 3.0e-14, 0.75, 0.3, 2.0)]
+    me_g = 9.1093837015e-28
+    erg_per_ev = 1.602176634e-12
+    for kT, tol in ((20.0, 1e-8), (150.0, 3e-6)):     # GL-64 error grows once kT > P (see above)
+        def integrand(E):
+            sig = 0.0
+            for (P, a, b, c, q) in shells:
+                if E >= P:
+                    sig += a * q * math.log(E / P) / (E * P) * (1 - b * math.exp(-c * (E / P - 1)))
+            v = math.sqrt(2 * E * erg_per_ev / me_g)
+            f = 2.0 / math.sqrt(math.pi) * kT**-1.5 * math.sqrt(E) * math.exp(-E / kT)
+            return sig * v * f
+        lo, hi = shells[0][0], shells[1][0]
+        v1, _ = integrate.quad(integrand, lo, hi, epsabs=0, epsrel=1e-12, limit=400)
+        v2, _ = integrate.quad(integrand, hi, hi + 200 * kT, epsabs=0, epsrel=1e-12, limit=400)
+        got = ionize.sigma_v_shells(kT, shells)
+        assert abs(got / (v1 + v2) - 1) < tol
+
+
+def test_ln_rate_shells_without_underflow():
+    shells = [(392.0, 4.5e-14, 0.2, 0.5, 2.0), (490.0, 4.5e-14, 0.0, 0.0, 1.0)]
+    ne = np.array([1e21, 3e20])
+    kT = np.array([60.0, 0.25])         # e^{-392/0.25} underflows in <sigma v>
+    ln = ionize.ln_rate_shells(kT, ne, shells)
+    assert np.all(np.isfinite(ln))
+    assert abs(ln[0] - math.log(ionize.rate_shells(kT[0], ne[0], shells))) < 1e-13 * abs(ln[0])
+    assert ionize.rate_shells(kT[1], ne[1], shells) == 0.0
+    # one subshell: the single-shell formula
+    one = [shells[0]]
+    assert np.allclose(ionize.ln_rate_shells(kT, ne, one), ionize.ln_rate_exact(kT, ne, 392.0, 2.0, 4.5e-14, 0.2, 0.5),
+                       rtol=1e-14, atol=0)
+
+
+def test_chain_events_poisson_for_equal_rates():
+    """With the same rate nu in every state the number of events in dt is a
+    Poisson(nu dt) count truncated at min(m, z_max - Z0)."""
+    n, m, zmax = 200_000, 4, 6
+    nu, dtp = 1.0, 1.3
+    U = workloads.rng(11).random((n, m))
+    Z0 = np.full(n, 1)
+    nev = ionize.chain_events(Z0, zmax, m, U, dtp, lambda Z, e: np.full(Z.shape, nu))
+    lam = nu * dtp
+    pk = [math.exp(-lam) * lam**k / math.factorial(k) for k in range(m)]
+    pk.append(1 - sum(pk))
+    for k in range(m + 1):
+        got = np.mean(nev == k)
+        assert abs(got - pk[k]) < 5 * math.sqrt(pk[k] * (1 - pk[k]) / n), (k, got, pk[k])
+    # truncation by the charge states left
+    nev = ionize.chain_events(np.full(n, zmax - 2), zmax, m, U, dtp, lambda Z, e: np.full(Z.shape, nu))
+    assert nev.max() == 2 and np.mean(nev == 2) == pytest.approx(1 - pk[0] - pk[1], abs=5e-3)
+
+
+def test_chain_events_two_rates_hypoexponential():
+    """Two events with rates nu1 != nu2 happen within dt with probability
+    1 - (nu2 e^{-nu1 dt} - nu1 e^{-nu2 dt}) / (nu2 - nu1)."""
+    n = 200_000
+    nu1, nu2, dtp = 0.8, 2.5, 1.0
+    U = workloads.rng(12).random((n, 2))
+    nev = ionize.chain_events(np.zeros(n, dtype=np.int64), 3, 2, U, dtp,
+                              lambda Z, e: np.where(Z == 0, nu1, nu2))
+    p2 = 1 - (nu2 * math.exp(-nu1 * dtp) - nu1 * math.exp(-nu2 * dtp)) / (nu2 - nu1)
+    p1 = 1 - math.exp(-nu1 * dtp) - p2
+    assert abs(np.mean(nev == 2) - p2) < 5 * math.sqrt(p2 * (1 - p2) / n)
+    assert abs(np.mean(nev == 1) - p1) < 5 * math.sqrt(p1 * (1 - p1) / n)
+
+
+def test_multi_event_step_forced_uniforms_and_ids():
+    cfg, st = _small_carbon_state()
+    cfg["species"][1]["max_events"] = 3
+    n_ion = st.species[1].n
+    ntot = sum(s.n for s in st.species)
+    n_e0 = st.species[0].n
+    s0 = st.copy()
+    d = ionize.ionize_step(s0, cfg, 0, 1, ntot, n_e0, uniforms=np.full((n_ion, 3), 1e-300), return_details=True)
+    # C2+ (z_max 6): every ion in a cell with electrons climbs three states
+    assert np.all(s0.species[1].zstate == 5)
+    assert s0.species[0].n == n_e0 + 3 * n_ion
+    ids = s0.species[0].id[n_e0:]
+    assert len(set(ids.tolist())) == ids.size
+    want = ntot + np.repeat((st.species[1].id - n_e0) * 6, 3) + np.tile([2, 3, 4], n_ion)
+    assert np.array_equal(ids, want)
+    s1 = st.copy()
+    assert ionize.ionize_step(s1, cfg, 0, 1, ntot, n_e0, uniforms=np.full((n_ion, 3), 1 - 2.0**-53)) == 0
+    # the first decision equals the single-event rule (u < 1 - e^{-nu dt}) away from ties
+    s2 = st.copy()
+    d = ionize.ionize_step(s2, cfg, 0, 1, ntot, n_e0, return_details=True)
+    u0 = d["uniforms"][:, 0]
+    clear = np.abs(u0 - d["prob"]) > 1e-12
+    assert np.array_equal((d["nevents"] > 0)[clear], (u0 < d["prob"])[clear])
+    assert np.all(d["nevents"] <= 3)
+
+
+def test_energy_loss_lowers_cell_temperature_by_the_event_energy():
+    """After the step, 3/2 N (kT_before - kT_after) = dE in every cell whose
+    electrons can pay (moments of the pre-existing electrons), the cell's mean
+    momentum is unchanged, and a cell that cannot pay is left at kT = 0."""
+    cfg, st = _small_carbon_state()
+    cfg["species"][1]["energy_loss"] = 1
+    ntot = sum(s.n for s in st.species)
+    n_e0 = st.species[0].n
+    g = st.grid
+    dV = g.dx * g.dy * g.dz
+    m0 = ionize.cell_moments(st, 0)
+    _, kT0 = ionize.density_temperature(m0, dV, 1e21)
+    s1 = st.copy()
+    u = np.where(np.arange(st.species[1].n) % 3 == 0, 0.0, 1.0)     # every third ion fires
+    d = ionize.ionize_step(s1, cfg, 0, 1, ntot, n_e0, uniforms=u, return_details=True)
+    assert d["fire"].sum() > 0
+    old = s1.copy()
+    for name in ("x", "y", "z", "ux", "uy", "uz", "w", "id"):
+        setattr(old.species[0], name, getattr(s1.species[0], name)[:n_e0].copy())
+    m1 = ionize.cell_moments(old, 0)
+    _, kT1 = ionize.density_temperature(m1, dV, 1e21)
+    N = m0[:, 0]
+    dE = d["dE"]
+    pay = (dE > 0) & (dE < 1.5 * N * kT0)
+    assert pay.sum() > 0
+    assert np.allclose(1.5 * N[pay] * (kT0[pay] - kT1[pay]), dE[pay], rtol=1e-9, atol=0)
+    assert np.allclose(kT1[dE == 0], kT0[dE == 0], rtol=1e-12, atol=0)
+    assert np.allclose(m1[:, 1:4], m0[:, 1:4], rtol=0, atol=1e-12 * np.abs(m0[:, 1:4]).max())
+    # a cell that cannot pay
+    f = ionize.energy_loss(st.copy(), 0, m0, kT0, np.where(np.arange(len(N)) == 0, 10 * 1.5 * N * kT0, 0.0))
+    assert f[0] == 0.0 and np.all(f[1:] == 1.0)

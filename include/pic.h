@@ -47,9 +47,10 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 3
+#define PIC_ABI_VERSION 4
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
+#define PIC_LOTZ_SHELLS 3
 #define PIC_SUPERCELL_X 8
 #define PIC_SUPERCELL_Y 8
 #define PIC_SUPERCELL_Z 4
@@ -98,6 +99,20 @@ typedef struct {
     int32_t reserved1;
 } pic_grid_t;
 
+/* One Lotz subshell of a charge state (Lotz 1968):
+ *   sigma_j(E) = a q ln(E/p) / (E p) [1 - b e^{-c (E/p - 1)}]  for E >= p.
+ * Subshell 0 is the outermost: its p_ev equals the state's ionization_ev and
+ * its q is > 0.  Further subshells have p_ev >= ionization_ev; q = 0 marks an
+ * unused slot (all later slots unused too).  a = 4.5e-14 cm^2 eV^2 with
+ * b = c = 0 is the plain single-shell form.  Limits: a > 0, 0 <= b <= 1, c >= 0. */
+typedef struct {
+    double p_ev;           /* binding energy (eV) */
+    double a;              /* cm^2 eV^2 */
+    double b, c;
+    int32_t q;             /* electrons in the subshell */
+    int32_t reserved;
+} pic_lotz_shell_t;
+
 /* One particle species.
  * Macro-particle weight w = density * dx*dy*dz / ppc.
  * Initial state (t = 0; u is stored at t - dt/2): exactly ppc particles per
@@ -108,9 +123,12 @@ typedef struct {
  * slots.  coincident_with >= 0 places slot s of every cell on slot s of that
  * (earlier or later) species, whose ppc must be >= this ppc.
  * z_max > 0 gives every particle a charge state Z (starting at z_init); its
- * charge is then charge * Z.  ionization_ev[Z] and lotz_q[Z] (Z < z_max) are
- * the ionisation energy and outer-shell electron count of state Z, and
- * ionize_into names the electron species that receives ionisation electrons. */
+ * charge is then charge * Z.  ionization_ev[Z] (Z < z_max) is the ionisation
+ * energy of state Z, lotz[Z] its Lotz subshells (below), and ionize_into
+ * names the electron species that receives ionisation electrons.
+ * max_events (0 or 1: one) caps the ionisations of one ion in one step and
+ * energy_loss = 1 makes the electrons of the ion's cell pay the ionisation
+ * energy (see pic_ionize). */
 typedef struct {
     double charge;         /* in e (per unit Z when z_max > 0) */
     double mass;           /* in m_e */
@@ -125,7 +143,9 @@ typedef struct {
     int32_t cap_ppc;       /* frame capacity in particles per cell (0: 3/2 ppc) */
     int32_t ionize_into;   /* species index of ionisation electrons, or -1 */
     double ionization_ev[PIC_MAX_ZSTATES];
-    int32_t lotz_q[PIC_MAX_ZSTATES];
+    pic_lotz_shell_t lotz[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];
+    int32_t max_events;    /* ionisations per ion per step (0 or 1: one; at most PIC_MAX_ZSTATES) */
+    int32_t energy_loss;   /* 1: the cell's electrons pay the ionisation energy */
 } pic_species_t;
 
 /* Device-memory provider.  alloc returns device memory of at least `bytes`
@@ -229,17 +249,17 @@ int pic_timing(pic_ctx* ctx, int enable, pic_timing_t* out);
 
 /* ------------------------------------------------------------------------
  * Monte Carlo electron-impact ionisation (the Monte Carlo atomic-physics step
- * the paper's introduction adds to the PIC cycle), single-shell Lotz model.
+ * the paper's introduction adds to the PIC cycle), Lotz model with subshells.
  *
  * For every ion species with z_max > 0 and ionize_into >= 0, per ion with
  * Z < z_max:
  *   - n_e and kT_e of the ion's cell from nearest-grid-point moments of the
  *     electrons of species ionize_into (drift removed):
  *       n_e = (sum w / dV) n_ref_cm3,  kT_e = m_e c^2 (sum w u^2 / sum w - |ubar|^2) / 3;
- *   - rate nu = n_e <sigma v>, <sigma v> the Lotz cross-section
- *     sigma(E) = a q ln(E/P) / (E P) (a = 4.5e-14 cm^2 eV^2, P = ionization_ev[Z],
- *     q = lotz_q[Z]) averaged over a Maxwellian, evaluated as
- *       vbar (a q / (P kT)) e^{-P/kT} sum_k w_k ln(1 + x_k kT / P)
+ *   - rate nu = n_e <sigma v>, <sigma v> the sum over the subshells lotz[Z][j]
+ *     of their cross-sections (pic_lotz_shell_t) averaged over a Maxwellian,
+ *     evaluated per subshell (p, a, b, c, q) as
+ *       vbar (a q / (p kT)) e^{-p/kT} sum_k w_k ln(1 + x_k r) (1 - b e^{-c x_k r}),  r = kT / p
  *     with the 64-point Gauss-Laguerre rule (x_k, w_k) in FP64 (PIC_RATE_EXACT),
  *     or by the learned surrogate (PIC_RATE_MLP, see below);
  *   - p = 1 - exp(-nu dt / omega_p) with omega_p the plasma frequency of
@@ -248,7 +268,20 @@ int pic_timing(pic_ctx* ctx, int enable, pic_timing_t* out);
  *     ion's position with its momentum and weight, id
  *       N0 + (ion id - first ion id) * z_max + (Z_new - 1)
  *     (N0 = number of particles at t = 0), appended to the same supercell's
- *     frames.  At most one event per ion per call.
+ *     frames.  At most one event per ion per call when max_events <= 1.
+ *   - max_events = m > 1: successive events in one call.  With n_e and kT_e
+ *     frozen, event e (e = 0, 1, ...) adds the waiting time
+ *     -ln(1 - u_e) / nu_{Z+e} and happens while the running time stays below
+ *     dt / omega_p, for at most m events (and Z < z_max).  u_e is word e % 4
+ *     of the Philox block of counter (id, species, 2, step) for e < 4, of
+ *     (id, species, 6, step) for e >= 4.  nu_Z of the first event comes from
+ *     the chosen mode; later events use the exact quadrature.  Electrons are
+ *     born as above, one per event.
+ *   - energy_loss = 1: per cell, dE = sum of w * ionization_ev[Z] over its
+ *     events; the electrons of species ionize_into that were in the cell
+ *     before the call get u <- ubar + f (u - ubar), f = sqrt(max(0,
+ *     1 - dE / (3/2 N kT_e))) with N = sum w and ubar, kT_e of the moments
+ *     above, so that the cell's kT_e drops by dE / (3/2 N).
  * ------------------------------------------------------------------------ */
 typedef struct {
     int64_t ions_active;   /* ions with Z < z_max at the start of the call */

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_MAX_SPECIES = 4
 PIC_MAX_ZSTATES = 8
+PIC_LOTZ_SHELLS = 3
 
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_OOM", -3: "PIC_ERR_HIP", -4: "PIC_ERR_CAPACITY",
           -5: "PIC_ERR_CFL", -6: "PIC_ERR_NONFINITE", -7: "PIC_ERR_STATE"}
@@ -23,12 +24,19 @@ class GridT(C.Structure):
                 ("gather", C.c_int32), ("reserved1", C.c_int32)]
 
 
+class LotzShellT(C.Structure):
+    _fields_ = [("p_ev", C.c_double), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("q", C.c_int32), ("reserved", C.c_int32)]
+
+
 class SpeciesT(C.Structure):
     _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("density", C.c_double), ("u_th", C.c_double),
                 ("drift_beta", C.c_double * 3), ("ppc", C.c_int32), ("layout", C.c_int32), ("mobile", C.c_int32),
                 ("coincident_with", C.c_int32), ("z_init", C.c_int32), ("z_max", C.c_int32),
                 ("cap_ppc", C.c_int32), ("ionize_into", C.c_int32),
-                ("ionization_ev", C.c_double * PIC_MAX_ZSTATES), ("lotz_q", C.c_int32 * PIC_MAX_ZSTATES)]
+                ("ionization_ev", C.c_double * PIC_MAX_ZSTATES),
+                ("lotz", (LotzShellT * PIC_LOTZ_SHELLS) * PIC_MAX_ZSTATES),
+                ("max_events", C.c_int32), ("energy_loss", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

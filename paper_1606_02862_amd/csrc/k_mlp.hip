@@ -38,9 +38,11 @@ __device__ inline float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Per charge state z: P_z, and the constant of the analytic prior
+// Per charge state z: P_z, and the constant of the analytic prior (the
+// outermost subshell's plain Lotz rate with e^{P/kT} E1(P/kT) replaced by
+// ln(1 + kT/P))
 // ln nu_prior = ln(n_e vbar a q / (P kT)) - P/kT + ln ln(1 + kT/P), with
-// vbar = c sqrt(8 kT / (pi m_e c^2)):  c_z = ln(c sqrt(8 / (pi m_e c^2)) a q_z / P_z).
+// vbar = c sqrt(8 kT / (pi m_e c^2)):  c_z = ln(c sqrt(8 / (pi m_e c^2)) a_z q_z / P_z).
 struct PriorTab {
     float P[PIC_MAX_ZSTATES], invP[PIC_MAX_ZSTATES], c[PIC_MAX_ZSTATES];
 };
@@ -49,10 +51,10 @@ __device__ inline void fill_prior(const IonTables& tab, PriorTab& T)
 {
     const int z = threadIdx.x;
     if (z < PIC_MAX_ZSTATES) {
-        const double P = z < tab.z_max ? tab.P[z] : 1.0, q = z < tab.z_max ? tab.q[z] : 1.0;
+        const double P = z < tab.z_max ? tab.P[z] : 1.0, aq = z < tab.z_max ? tab.aq[z][0] : LOTZ_A;
         T.P[z] = (float)P;
         T.invP[z] = (float)(1.0 / P);
-        T.c[z] = (float)log(C_CM_S * sqrt(8.0 / (M_PI * ME_C2_EV)) * LOTZ_A * q / P);
+        T.c[z] = (float)log(C_CM_S * sqrt(8.0 / (M_PI * ME_C2_EV)) * aq / P);
     }
 }
 
@@ -213,10 +215,10 @@ __device__ inline float forward64(const Net& n, int lane, float x0, float x1, in
 // Exact FP64 rate for the (rare) samples outside the trained range, kept out
 // of line so that its register footprint does not lower the occupancy of the
 // surrogate path.
-__device__ __noinline__ double fallback_rate(double kT, double ne, double P, double q, const double* glx,
+__device__ __noinline__ double fallback_rate(double kT, double ne, const IonTables& tab, int Z, const double* glx,
                                             const double* glw)
 {
-    return rate_exact(kT, ne, P, q, glx, glw);
+    return rate_exact(kT, ne, tab, Z, glx, glw);
 }
 
 struct MlpArgs {
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_fallback(GridView g, SpeciesView
         const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
                            (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
         const int Z = ion.zs[p];
-        nu[p] = rate_exact(kT[gi], ne[gi], tab.P[Z], tab.q[Z], glx, glw);
+        nu[p] = rate_exact(kT[gi], ne[gi], tab, Z, glx, glw);
     }
 }
 
@@ -333,8 +335,10 @@ __global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* 
 {
     __shared__ double glx[GL_NODES], glw[GL_NODES];
     __shared__ PriorTab PT;
+    __shared__ IonTables s_tab;  // the out-of-line fallback reads the tables from LDS
     const int tid = threadIdx.x, lane = tid & 63;
     if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
+    if (tid == 0) s_tab = tab;
     fill_prior(tab, PT);
     Net net;
     load_net(m.params, lane, net);
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* 
             if (inr) {
                 out[i] = (double)(prior + m.mu + m.s * y);
             } else if (Z >= 0 && Z < tab.z_max) {
-                const double v = fallback_rate(kT[i], ne[i], tab.P[Z], tab.q[Z], glx, glw);
+                const double v = fallback_rate(kT[i], ne[i], s_tab, Z, glx, glw);
                 out[i] = v > 0.0 ? log(v) : -INFINITY;
             } else {
                 out[i] = -INFINITY;
@@ -401,10 +405,10 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_gen(int64_t n, uint64_t seed, Mlp
     x[0] = (float)((lt - 2.0) * 0.5);
     x[1] = (float)((ln10n - 21.0) * 0.5);
     for (int k = 0; k < 6; ++k) x[2 + k] = (k == Z) ? 1.0f : 0.0f;
-    const double P = tab.P[Z], q = tab.q[Z];
+    const double P = tab.P[Z], aq = tab.aq[Z][0];
     const double z = P / kT;
-    const double prior = log(ne * vbar_cm_s(kT) * LOTZ_A * q / (P * kT)) - z + log(log1p(1.0 / z));
-    r[i] = ln_rate_exact(kT, ne, P, q, glx, glw) - prior;
+    const double prior = log(ne * vbar_cm_s(kT) * aq / (P * kT)) - z + log(log1p(1.0 / z));
+    r[i] = ln_rate_exact(kT, ne, tab, Z, glx, glw) - prior;
 }
 
 hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTables& tab, const double* gl, float* X,

@@ -44,6 +44,9 @@ struct pic_ctx {
     double* gl = nullptr;                    // 64 nodes then 64 weights
     double* ne = nullptr;                    // per-cell n_e (cm^-3)
     double* kT = nullptr;                    // per-cell kT_e (eV)
+    double* mom4 = nullptr;                  // per-cell sum w and mean u (energy loss)
+    double* de = nullptr;                    // per-cell ionisation energy to pay (energy loss)
+    int32_t* old_count = nullptr;            // per-supercell electron count before the appends
     double* nu[PIC_MAX_SPECIES] = {};        // per ion slot rate (1/s)
     unsigned long long* fbl[PIC_MAX_SPECIES] = {};  // per ion slot: surrogate fallback list
     unsigned long long* counters = nullptr;  // active, ionised, fallback
@@ -173,9 +176,26 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
         if (p.z_max < 0 || p.z_max > PIC_MAX_ZSTATES - 1) return fail(nullptr, PIC_ERR_ARG, "species %d: z_max", s);
         if (p.z_max > 0) {
             if (p.z_init < 0 || p.z_init > p.z_max) return fail(nullptr, PIC_ERR_ARG, "species %d: z_init", s);
-            for (int z = 0; z < p.z_max; ++z)
-                if (!finite_pos(p.ionization_ev[z]) || p.lotz_q[z] < 0)
+            for (int z = 0; z < p.z_max; ++z) {
+                if (!finite_pos(p.ionization_ev[z]))
                     return fail(nullptr, PIC_ERR_ARG, "species %d: ionisation data of state %d", s, z);
+                const pic_lotz_shell_t* L = p.lotz[z];
+                if (L[0].q <= 0 || L[0].p_ev != p.ionization_ev[z])
+                    return fail(nullptr, PIC_ERR_ARG,
+                                "species %d: lotz subshell 0 of state %d must have q > 0 and p_ev = ionization_ev", s, z);
+                bool end = false;
+                for (int j = 0; j < PIC_LOTZ_SHELLS; ++j) {
+                    if (L[j].q < 0) return fail(nullptr, PIC_ERR_ARG, "species %d: lotz q < 0 (state %d)", s, z);
+                    if (L[j].q == 0) { end = true; continue; }
+                    if (end) return fail(nullptr, PIC_ERR_ARG, "species %d: lotz subshell after an unused slot (state %d)", s, z);
+                    if (!(L[j].p_ev >= p.ionization_ev[z]) || !std::isfinite(L[j].p_ev) || !finite_pos(L[j].a) ||
+                        !(L[j].b >= 0.0 && L[j].b <= 1.0) || !(L[j].c >= 0.0 && std::isfinite(L[j].c)))
+                        return fail(nullptr, PIC_ERR_ARG, "species %d: lotz subshell %d of state %d (p_ev, a, b, c)", s, j, z);
+                }
+            }
+            if (p.max_events < 0 || p.max_events > PIC_MAX_ZSTATES)
+                return fail(nullptr, PIC_ERR_ARG, "species %d: max_events", s);
+            if (p.energy_loss != 0 && p.energy_loss != 1) return fail(nullptr, PIC_ERR_ARG, "species %d: energy_loss", s);
         }
         if (p.ionize_into != -1) {
             if (p.ionize_into < 0 || p.ionize_into >= n || p.ionize_into == s || p.z_max == 0)
@@ -280,6 +300,11 @@ int alloc_ionisation(pic_ctx* c)
             !(m.v = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.grad = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)))
             return fail(c, PIC_ERR_OOM, "device allocation of the surrogate failed");
         HIPCHK(c, launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream));
+        if (c->sp[s].desc.energy_loss && !c->de) {
+            if (!(c->mom4 = (double*)dev_alloc(c, N * 4 * 8)) || !(c->de = (double*)dev_alloc(c, N * 8)) ||
+                !(c->old_count = (int32_t*)dev_alloc(c, (size_t)c->g.nsc * 4)))
+                return fail(c, PIC_ERR_OOM, "device allocation of energy-loss buffers failed");
+        }
     }
     const double* w;
     const double* x = gauss_laguerre_nodes(&w);
@@ -297,7 +322,15 @@ IonTables ion_tables(const pic_ctx* c, int s)
     const pic_species_t& d = c->sp[s].desc;
     for (int z = 0; z < PIC_MAX_ZSTATES; ++z) {
         t.P[z] = z < d.z_max ? d.ionization_ev[z] : 1.0;
-        t.q[z] = z < d.z_max ? (double)d.lotz_q[z] : 0.0;
+        for (int j = 0; j < PIC_LOTZ_SHELLS; ++j) {
+            const pic_lotz_shell_t& L = d.lotz[z][j];
+            const bool used = z < d.z_max && L.q > 0;
+            t.sp[z][j] = used ? L.p_ev : 1.0;
+            t.aq[z][j] = used ? L.a * L.q : 0.0;
+            t.sb[z][j] = used ? L.b : 0.0;
+            t.sc[z][j] = used ? L.c : 0.0;
+            if (used) t.ns[z] = j + 1;
+        }
     }
     t.z_max = d.z_max;
     return t;
@@ -921,7 +954,11 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         const IonTables tab = ion_tables(c, s);
         HIPCHK(c, launch_zero_i32((int32_t*)c->counters, 8, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[0], c->stream));
-        HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, c->stream));
+        const pic_species_t& d = c->sp[s].desc;
+        const bool eloss = d.energy_loss != 0;
+        HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, eloss ? c->mom4 : nullptr,
+                                 c->stream));
+        if (eloss) HIPCHK(c, launch_zero_f64(c->de, (int64_t)c->grid.nx * c->grid.ny * c->grid.nz, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
         if (mode == PIC_RATE_EXACT)
             HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->counters, c->stream));
@@ -936,7 +973,12 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         a.ion_id_offset = c->sp[s].id_offset;
         a.id_base_new = n0;
         a.dt_phys = dt_phys;
-        HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], c->counters, c->stream));
+        a.max_events = d.max_events;
+        a.energy_loss = eloss ? 1 : 0;
+        const DrawBuffers db{c->ne, c->kT, c->gl, eloss ? c->mom4 : nullptr, eloss ? c->de : nullptr,
+                             eloss ? c->old_count : nullptr};
+        HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], db, c->counters, c->stream));
+        if (eloss) HIPCHK(c, launch_energy_loss(c->g, c->sp[e].v, db, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[3], c->stream));
         unsigned long long cnt[4];
         HIPCHK(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
@@ -966,7 +1008,7 @@ int pic_cell_moments(pic_ctx* c, int s, double* ne_out, double* kT_out)
     const int e = c->sp[s].desc.ionize_into;
     const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
     const double dV = c->grid.dx * c->grid.dy * c->grid.dz;
-    HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, c->stream));
+    HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, nullptr, c->stream));
     if (ne_out) HIPCHK(c, hipMemcpyAsync(ne_out, c->ne, N * 8, hipMemcpyDeviceToHost, c->stream));
     if (kT_out) HIPCHK(c, hipMemcpyAsync(kT_out, c->kT, N * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

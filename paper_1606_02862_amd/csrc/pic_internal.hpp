@@ -147,9 +147,14 @@ constexpr double ME_C2_EV = 510998.95;       // electron rest energy (eV)
 constexpr double C_CM_S = 2.99792458e10;     // speed of light (cm/s)
 constexpr double LOTZ_A = 4.5e-14;           // Lotz constant (cm^2 eV^2)
 
+// Lotz subshells per charge state Z (subshell 0 the outermost, sp[Z][0] = P[Z]).
 struct IonTables {
-    double P[PIC_MAX_ZSTATES];  // ionisation energy of state Z (eV)
-    double q[PIC_MAX_ZSTATES];  // outer-shell electrons of state Z
+    double P[PIC_MAX_ZSTATES];                    // ionisation energy of state Z (eV)
+    double sp[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];  // subshell binding energies (eV)
+    double aq[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];  // a q (cm^2 eV^2)
+    double sb[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];  // b
+    double sc[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];  // c
+    int ns[PIC_MAX_ZSTATES];                      // subshells in use
     int z_max;
 };
 
@@ -160,20 +165,34 @@ struct DrawArgs {
     int64_t ion_id_offset;
     int64_t id_base_new;
     double dt_phys;             // dt / omega_p in seconds
+    int max_events;             // <= 1: one event per ion; else the waiting-time chain
+    int energy_loss;            // 1: accumulate w * P per cell into de
+};
+// Per-step ionisation buffers the draw and energy-loss kernels share.
+struct DrawBuffers {
+    const double* ne;           // per cell n_e (cm^-3)
+    const double* kT;           // per cell kT_e (eV)
+    const double* gl;           // Gauss-Laguerre rule (later events' exact rates)
+    const double* mom4;         // per cell N = sum w and mean u (energy loss), or nullptr
+    double* de;                 // per cell sum of w * P over the events (energy loss), or nullptr
+    int32_t* old_count;         // per supercell electron count before the appends (energy loss), or nullptr
 };
 
 // host: the 64-point Gauss-Laguerre rule (nodes; weights through *w)
 const double* gauss_laguerre_nodes(const double** w);
 
+// mom4: per cell (sum w, mean ux, uy, uz), or nullptr
 hipError_t launch_moments(const GridView& g, const SpeciesView& e, double n_ref_over_dv, double* ne, double* kT,
-                          hipStream_t st);
+                          double* mom4, hipStream_t st);
 hipError_t launch_rate_exact(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
                              const double* kT, double* nu, const double* gl, unsigned long long* counters,
                              hipStream_t st);
 hipError_t launch_ln_rate_exact(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
                                 const double* gl, double* out, hipStream_t st);
 hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
-                              const DrawArgs& a, const double* nu, unsigned long long* counters, hipStream_t st);
+                              const DrawArgs& a, const double* nu, const DrawBuffers& b, unsigned long long* counters,
+                              hipStream_t st);
+hipError_t launch_energy_loss(const GridView& g, const SpeciesView& el, const DrawBuffers& b, hipStream_t st);
 
 // ---------------------------------------------------------------- surrogate
 struct MlpLaunch {

@@ -29,6 +29,7 @@ def gauss_laguerre64():
 
 _SHAPE = {"cic": 1, "tsc": 2, "pcs": 3}
 _PRECISION = {"fp32": 0, "fp64": 1}
+LOTZ_A = 4.5e-14  # cm^2 eV^2, the plain Lotz constant
 
 
 def grid_struct(cfg: dict) -> A.GridT:
@@ -59,9 +60,18 @@ def species_structs(cfg: dict):
         s.z_init, s.z_max = sp["z_init"], sp["z_max"]
         s.cap_ppc = sp.get("cap_ppc") or 0
         s.ionize_into = sp.get("ionize_into", -1)
-        for z, (ev, q) in enumerate(zip(sp["ionization_ev"], sp["lotz_q"])):
+        s.max_events = sp.get("max_events", 1)
+        s.energy_loss = int(sp.get("energy_loss", 0))
+        for z, ev in enumerate(sp["ionization_ev"]):
             s.ionization_ev[z] = ev
-            s.lotz_q[z] = q
+            # "lotz_shells"[z]: dicts (p_ev, q, and a, b, c defaulting to the plain
+            # form); otherwise one subshell (ionization_ev, 4.5e-14, 0, 0, lotz_q)
+            shells = (sp["lotz_shells"][z] if sp.get("lotz_shells")
+                      else [dict(p_ev=ev, q=sp["lotz_q"][z])])
+            for j, sh in enumerate(shells):
+                L = s.lotz[z][j]
+                L.p_ev, L.q = sh["p_ev"], sh["q"]
+                L.a, L.b, L.c = sh.get("a", LOTZ_A), sh.get("b", 0.0), sh.get("c", 0.0)
     return arr
 
 

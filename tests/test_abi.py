@@ -75,6 +75,29 @@ def test_init_rejects_bad_arguments(A, what, mutate, needle):
     assert needle in msg, msg
 
 
+def _set(obj, **kw):
+    for k, v in kw.items():
+        setattr(obj, k, v)
+
+
+@pytest.mark.parametrize("what,mutate,needle", [
+    ("subshell 0 without electrons", lambda g, s: _set(s[1].lotz[2][0], q=0), "subshell 0"),
+    ("subshell 0 off the ionisation energy", lambda g, s: _set(s[1].lotz[2][0], p_ev=50.0), "subshell 0"),
+    ("inner subshell below the threshold", lambda g, s: _set(s[1].lotz[2][1], p_ev=10.0, a=4.5e-14, q=2), "subshell 1"),
+    ("b above 1", lambda g, s: _set(s[1].lotz[0][0], b=1.5), "subshell 0"),
+    ("negative c", lambda g, s: _set(s[1].lotz[0][0], c=-0.1), "subshell 0"),
+    ("zero a", lambda g, s: _set(s[1].lotz[3][0], a=0.0), "subshell 0"),
+    ("gap in subshells", lambda g, s: _set(s[1].lotz[1][2], p_ev=300.0, a=4.5e-14, q=2), "unused slot"),
+    ("max_events", lambda g, s: _set(s[1], max_events=9), "max_events"),
+    ("energy_loss", lambda g, s: _set(s[1], energy_loss=2), "energy_loss"),
+])
+def test_init_rejects_bad_ionisation_data(A, what, mutate, needle):
+    rc, h, msg = _init(A, workloads.reduced(3, 8, 8, 4), mutate=mutate)
+    assert rc == A.PIC_ERR_ARG, what
+    assert h.value is None
+    assert needle in msg, msg
+
+
 def test_init_rejects_bad_shape_and_species_count(A):
     rc, _, msg = _init(A, workloads.config(0), shape=4)
     assert rc == A.PIC_ERR_ARG and "shape" in msg
@@ -96,7 +119,7 @@ def test_null_handles(A):
     lib = A.load()
     assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
     assert lib.pic_destroy(None) == A.PIC_OK
-    assert lib.pic_abi_version() == 3
+    assert lib.pic_abi_version() == 4
     m = A.MomentsT()
     assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
 

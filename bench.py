@@ -121,26 +121,45 @@ def copy_calibration() -> int:
 def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     """Monte Carlo ionisation on the 128^3 electron-carbon workload: GPU time
     of the rate stage and of the whole step with the exact FP64 GL-64
-    quadrature and with the BF16-MFMA surrogate (trained first on the GPU),
-    and the surrogate's rate error against the exact quadrature."""
+    quadrature, with the BF16-MFMA surrogate (trained first on the GPU) and
+    with the tabulated rate, and their rate errors against the exact
+    quadrature."""
     import numpy as np
     cfg = workloads.config(3)
     gc = cfg["grid"]
     ncell = gc["nx"] * gc["ny"] * gc["nz"]
     pic = P.Pic(cfg)
     rep = pic.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **workloads.MLP_TRAIN)
+    trained = pic.mlp_get_params(1)
     pic.step(2)
     out = {"workload": workloads.config(4)["workload"], "ions": ncell * cfg["species"][1]["ppc"],
            "electrons_initial": ncell * cfg["species"][0]["ppc"], "train": rep}
-    for mode in ("exact", "mlp"):
-        runs = [pic.ionize(mode) for _ in range(repeats)]
+
+    def one_call(mode):
+        # a fresh handle per call: every mode and repeat ionises the same state
+        # (same cells, charge states and Philox draws)
+        h = P.Pic(cfg)
+        if mode == "mlp":
+            h.mlp_set_params(1, *trained)
+        if mode == "table":
+            h.rate_eval("table", 1, [100.0], [1e21], [2])   # builds the table (once per handle)
+        h.step(2)
+        r = h.ionize(mode)
+        h.close()
+        return r
+
+    for mode in ("exact", "mlp", "table"):
+        runs = [one_call(mode) for _ in range(repeats)]
         out[mode] = {"rate_ms": min(r["rate_ms"] for r in runs), "total_ms": min(r["total_ms"] for r in runs),
                      "ionized_per_call": [r["ionized"] for r in runs], "fallback": runs[-1]["fallback"],
                      "ions_active": runs[-1]["ions_active"]}
     out["rate_stage_speedup"] = out["exact"]["rate_ms"] / out["mlp"]["rate_ms"]
     # the whole pic_ionize (cell moments + rate + draw/append; moments and draw are the same in both modes)
     out["whole_step_speedup"] = out["exact"]["total_ms"] / out["mlp"]["total_ms"]
-    out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3) for m in ("exact", "mlp")}
+    out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3)
+                                    for m in ("exact", "mlp", "table")}
+    out["table_rate_stage_speedup"] = out["exact"]["rate_ms"] / out["table"]["rate_ms"]
+    out["table_whole_step_speedup"] = out["exact"]["total_ms"] / out["table"]["total_ms"]
     # error of the surrogate against the exact quadrature (the judge)
     T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)
     ex = pic.rate_eval("exact", 1, T, ne, Z)
@@ -156,6 +175,7 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     def stats(r):
         return {"median": float(np.median(r)), "p99": float(np.quantile(r, 0.99)), "max": float(r.max())}
     out["mlp_error_heldout"] = stats(rel)
+    out["table_error_heldout"] = stats(np.abs(np.expm1(pic.rate_eval("table", 1, T, ne, Z) - ex)))
     out["prior_only_error_heldout"] = stats(relp)
     # live population: every cell's (n_e, kT_e) with the charge states present
     ne_c, kT_c = pic.cell_moments(1)

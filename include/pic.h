@@ -70,7 +70,9 @@ enum pic_status {
  * and 3 (PCS), used for both the field gather and the Esirkepov deposit. */
 typedef enum { PIC_SHAPE_CIC = 1, PIC_SHAPE_TSC = 2, PIC_SHAPE_PCS = 3 } pic_shape_t;
 typedef enum { PIC_LAYOUT_UNIFORM = 0, PIC_LAYOUT_SHEAR = 1, PIC_LAYOUT_BEAMS = 2 } pic_layout_t;
-typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1 } pic_rate_mode_t;
+/* Ionisation rate: the exact quadrature, the learned surrogate, or a table in
+ * ln kT read by cubic interpolation (see pic_ionize). */
+typedef enum { PIC_RATE_EXACT = 0, PIC_RATE_MLP = 1, PIC_RATE_TABLE = 2 } pic_rate_mode_t;
 /* Real type of particles, fields and currents on the device.  FP64 is the
  * double-precision variant of the PIC cycle that the paper benchmarks beside
  * single precision (section "Evaluation"): the same kernels instantiated in
@@ -261,7 +263,13 @@ int pic_timing(pic_ctx* ctx, int enable, pic_timing_t* out);
  *     evaluated per subshell (p, a, b, c, q) as
  *       vbar (a q / (p kT)) e^{-p/kT} sum_k w_k ln(1 + x_k r) (1 - b e^{-c x_k r}),  r = kT / p
  *     with the 64-point Gauss-Laguerre rule (x_k, w_k) in FP64 (PIC_RATE_EXACT),
- *     or by the learned surrogate (PIC_RATE_MLP, see below);
+ *     by the learned surrogate (PIC_RATE_MLP, see below), or from a table
+ *     (PIC_RATE_TABLE): per state Z, h_Z = ln of the subshell sum
+ *     sum_j (a_j q_j / p_j) e^{-(p_j - P)/kT} S_j at 1024 points uniform in
+ *     ln kT over [1e-2, 1e6] eV, built on the GPU by the same quadrature at
+ *     the first call that uses it, read by Catmull-Rom cubic interpolation:
+ *     nu = n_e vbar / kT e^{h_Z - P/kT} (interpolation error below 1e-7 in
+ *     ln nu); the exact quadrature outside that range;
  *   - p = 1 - exp(-nu dt / omega_p) with omega_p the plasma frequency of
  *     n_ref_cm3; the ion ionises when the Philox uniform of counter
  *     (id, species, 2, step) is below p: Z += 1 and an electron is born at the
@@ -286,7 +294,7 @@ int pic_timing(pic_ctx* ctx, int enable, pic_timing_t* out);
 typedef struct {
     int64_t ions_active;   /* ions with Z < z_max at the start of the call */
     int64_t ionized;       /* ionisation events */
-    int64_t fallback;      /* PIC_RATE_MLP: ions rated by the exact quadrature instead */
+    int64_t fallback;      /* PIC_RATE_MLP / _TABLE: ions rated by the exact quadrature instead */
     int64_t electrons;     /* particles of the receiving species after the call */
     double rate_ms;        /* GPU time of the rate stage (HIP events, handle's stream) */
     double total_ms;       /* GPU time of the whole call */

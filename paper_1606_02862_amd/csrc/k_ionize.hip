@@ -186,8 +186,12 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
         const int64_t p = base + t;
         const int Z0 = ion.zs[p];
         if (Z0 >= tab.z_max) continue;
-        const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
-                           (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
+        // the ion's cell, for later events' rates and the energy account only
+        const bool need_cell = a.max_events > 1 || a.energy_loss;
+        const int64_t gi = need_cell ? (int64_t)(scx * SX + (int)ion.x[p]) +
+                                           (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) +
+                                                            (int64_t)g.ny * (scz * SZ + (int)ion.z[p]))
+                                     : 0;
         const uint32_t id = ion.id[p];
         const int nev = ion_events(tab, a, id, Z0, nu[p], a.max_events > 1 ? db.kT[gi] : 0.0,
                                    a.max_events > 1 ? db.ne[gi] : 0.0, glx, glw);

@@ -325,6 +325,13 @@ hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonT
     hipLaunchKernelGGL(k_rate_mlp, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, counters, fb_list);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_rate_fallback(g, ion, tab, ne, kT, nu, gl, fb_list, counters, st);
+}
+
+hipError_t launch_rate_fallback(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
+                                const double* kT, double* nu, const double* gl, const unsigned long long* fb_list,
+                                const unsigned long long* counters, hipStream_t st)
+{
     hipLaunchKernelGGL(k_rate_fallback, dim3(256), dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, gl, fb_list, counters);
     return hipGetLastError();
 }

@@ -48,6 +48,8 @@ struct pic_ctx {
     double* de = nullptr;                    // per-cell ionisation energy to pay (energy loss)
     int32_t* old_count = nullptr;            // per-supercell electron count before the appends
     double* nu[PIC_MAX_SPECIES] = {};        // per ion slot rate (1/s)
+    double* rtab[PIC_MAX_SPECIES] = {};      // tabulated subshell sums (PIC_RATE_TABLE), built at first use
+    bool rtab_ready[PIC_MAX_SPECIES] = {};
     unsigned long long* fbl[PIC_MAX_SPECIES] = {};  // per ion slot: surrogate fallback list
     unsigned long long* counters = nullptr;  // active, ionised, fallback
     hipEvent_t iev[4] = {};
@@ -293,6 +295,7 @@ int alloc_ionisation(pic_ctx* c)
     for (int s = 0; s < c->nsp; ++s) {
         if (c->sp[s].desc.z_max == 0) continue;
         if (!(c->nu[s] = (double*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)) ||
+            !(c->rtab[s] = (double*)dev_alloc(c, (size_t)PIC_MAX_ZSTATES * RATE_TABLE_N * 8)) ||
             !(c->fbl[s] = (unsigned long long*)dev_alloc(c, (size_t)c->g.nsc * c->sp[s].v.cap * 8)))
             return fail(c, PIC_ERR_OOM, "device allocation of ionisation rates failed");
         pic_ctx::Mlp& m = c->mlp[s];
@@ -334,6 +337,15 @@ IonTables ion_tables(const pic_ctx* c, int s)
     }
     t.z_max = d.z_max;
     return t;
+}
+
+// Build the species' rate table on the handle's stream at its first use.
+int ensure_rate_table(pic_ctx* c, int s)
+{
+    if (c->rtab_ready[s]) return PIC_OK;
+    HIPCHK(c, launch_rate_table_build(ion_tables(c, s), c->gl, c->rtab[s], c->stream));
+    c->rtab_ready[s] = true;
+    return PIC_OK;
 }
 
 MlpLaunch mlp_launch(const pic_ctx* c, int s)
@@ -933,13 +945,18 @@ int pic_set_fields64(pic_ctx* c, const double* E, const double* B, const double*
 int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
-    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP) return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
+    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP && mode != PIC_RATE_TABLE)
+        return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
     int nion = 0;
     for (int s = 0; s < c->nsp; ++s)
         if (ionising(c, s)) {
             ++nion;
             if (mode == PIC_RATE_MLP && !c->mlp[s].ready)
                 return fail(c, PIC_ERR_STATE, "species %d: no trained or loaded surrogate", s);
+            if (mode == PIC_RATE_TABLE) {
+                const int rc = ensure_rate_table(c, s);
+                if (rc != PIC_OK) return rc;
+            }
         }
     if (!nion) return fail(c, PIC_ERR_STATE, "no ionising species (z_max > 0 with ionize_into >= 0)");
     pic_ionize_stats_t st{};
@@ -962,6 +979,9 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
         if (mode == PIC_RATE_EXACT)
             HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->counters, c->stream));
+        else if (mode == PIC_RATE_TABLE)
+            HIPCHK(c, launch_rate_table(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->rtab[s], c->gl, c->counters,
+                                        c->fbl[s], c->stream));
         else
             HIPCHK(c, launch_rate_mlp(c->g, c->sp[s].v, tab, mlp_launch(c, s), c->ne, c->kT, c->nu[s], c->gl,
                                       c->counters, c->fbl[s], c->stream));
@@ -1019,9 +1039,14 @@ int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const doub
                   const int32_t* Z, double* ln_rate)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
-    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP) return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
+    if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP && mode != PIC_RATE_TABLE)
+        return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
     if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
     if (n < 0 || (n > 0 && (!kT || !ne || !Z || !ln_rate))) return fail(c, PIC_ERR_ARG, "bad sample arrays");
+    if (mode == PIC_RATE_TABLE) {
+        const int rc = ensure_rate_table(c, s);
+        if (rc != PIC_OK) return rc;
+    }
     if (mode == PIC_RATE_MLP && !c->mlp[s].ready) return fail(c, PIC_ERR_STATE, "species %d: no surrogate", s);
     if (n == 0) return PIC_OK;
     double* d = (double*)dev_alloc(c, (size_t)n * 3 * 8);
@@ -1038,7 +1063,9 @@ int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const doub
     const IonTables tab = ion_tables(c, s);
     if (e == hipSuccess)
         e = mode == PIC_RATE_EXACT ? launch_ln_rate_exact(n, d, d + n, dz, tab, c->gl, d + 2 * n, c->stream)
-                                   : launch_ln_rate_mlp(n, d, d + n, dz, tab, mlp_launch(c, s), c->gl, d + 2 * n, c->stream);
+            : mode == PIC_RATE_TABLE
+                ? launch_ln_rate_table(n, d, d + n, dz, tab, c->rtab[s], c->gl, d + 2 * n, c->stream)
+                : launch_ln_rate_mlp(n, d, d + n, dz, tab, mlp_launch(c, s), c->gl, d + 2 * n, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ln_rate, d + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = fail(c, PIC_ERR_HIP, "rate evaluation: %s", hipGetErrorString(e));

@@ -178,6 +178,18 @@ struct DrawBuffers {
     int32_t* old_count;         // per supercell electron count before the appends (energy loss), or nullptr
 };
 
+// Tabulated rate (PIC_RATE_TABLE): RATE_TABLE_N nodes per charge state,
+// uniform in ln kT, covering [RATE_TABLE_TMIN, RATE_TABLE_TMAX] eV.
+constexpr int RATE_TABLE_N = 1024;
+constexpr double RATE_TABLE_TMIN = 1e-2, RATE_TABLE_TMAX = 1e6;
+hipError_t launch_rate_table_build(const IonTables& tab, const double* gl, double* table, hipStream_t st);
+// fb_list: one entry per ion slot, for the ions outside the table's range
+hipError_t launch_rate_table(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
+                             const double* kT, double* nu, const double* table, const double* gl,
+                             unsigned long long* counters, unsigned long long* fb_list, hipStream_t st);
+hipError_t launch_ln_rate_table(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
+                                const double* table, const double* gl, double* out, hipStream_t st);
+
 // host: the 64-point Gauss-Laguerre rule (nodes; weights through *w)
 const double* gauss_laguerre_nodes(const double** w);
 
@@ -215,6 +227,10 @@ struct MlpStep {
 hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,
                            const double* ne, const double* kT, double* nu, const double* gl,
                            unsigned long long* counters, unsigned long long* fb_list, hipStream_t st);
+// The exact FP64 rate for the counters[2] ions listed in fb_list.
+hipError_t launch_rate_fallback(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
+                                const double* kT, double* nu, const double* gl, const unsigned long long* fb_list,
+                                const unsigned long long* counters, hipStream_t st);
 hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
                               const MlpLaunch& ml, const double* gl, double* out, hipStream_t st);
 hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTables& tab, const double* gl, float* X,

@@ -11,7 +11,7 @@ import numpy as np
 from . import _capi as A
 
 _LAYOUT = {"uniform": 0, "shear": 1, "beams": 2}
-_MODE = {"exact": 0, "mlp": 1}
+_MODE = {"exact": 0, "mlp": 1, "table": 2}
 
 
 def _dptr(a: np.ndarray):

@@ -193,3 +193,55 @@ def test_ionize_energy_loss_matches_oracle(P):
     new = ~old
     for a in ("ux", "uy", "uz"):
         assert np.array_equal(getattr(eg, a)[new], getattr(er, a)[new]), a
+
+
+# ---------------------------------------------------------------------------
+# tabulated rate (PIC_RATE_TABLE)
+
+@pytest.mark.parametrize("rich", [False, True])
+def test_table_rate_matches_oracle(P, rich):
+    """Catmull-Rom on 1024 nodes in ln kT: ln nu within 1e-7 of the exact
+    quadrature inside [1e-2, 1e6] eV (the cubic's error bound there is
+    ~3e-8); outside, the exact quadrature itself (1e-12)."""
+    cfg = _rich_cfg() if rich else workloads.reduced(3, 16, 16, 8)
+    sh = ionize.lotz_shells(cfg["species"][1])
+    T, ne, Z = workloads.loguniform_rate_inputs(23, 40000, t_range=(2e-3, 5e6), n_range=(1e18, 1e24))
+    with P.Pic(cfg) as pic:
+        got = pic.rate_eval("table", 1, T, ne, Z)
+    want = np.empty_like(T)
+    for z in range(6):
+        m = Z == z
+        want[m] = ionize.ln_rate_shells(T[m], ne[m], sh[z])
+    fin = np.isfinite(want)
+    inside = fin & (T >= 1e-2) & (T <= 1e6)
+    outside = fin & ~inside
+    err_in = np.abs(got[inside] - want[inside]).max()
+    err_out = np.abs(got[outside] - want[outside]).max()
+    _print("table ln-rate err inside", err_in, "outside", err_out, "n", inside.sum(), outside.sum())
+    assert inside.sum() > 30000 and outside.sum() > 500
+    assert err_in < 1e-7
+    assert err_out < 1e-12 * np.maximum(1.0, np.abs(want[outside])).max()
+
+
+def test_ionize_table_matches_oracle(P):
+    """Decisions from table rates equal the oracle's (exact rates) except
+    where the uniform is within the table's error (1e-7 relative) of p."""
+    cfg = _rich_cfg(n_ref=1e24)
+    n_e0, n_c0 = _counts(cfg)
+    with P.Pic(cfg) as pic:
+        s0 = _shared(pic, cfg)
+        ref = s0.copy()
+        d = ionize.ionize_step(ref, cfg, 0, 1, n_e0 + n_c0, n_e0, return_details=True)
+        stats = pic.ionize("table")
+        got = parity.pull_state(pic, s0)
+    _print("table: ionised gpu/ref", stats["ionized"], int(d["fire"].sum()), "exact fallback", stats["fallback"])
+    assert d["fire"].sum() > 100
+    zg, zr = got.species[1].zstate, ref.species[1].zstate
+    differ = np.nonzero(zg != zr)[0]
+    assert len(differ) <= 2
+    for k in differ:
+        assert abs(d["uniforms"][k] - d["prob"][k]) < 1e-7 * d["prob"][k]
+    if len(differ) == 0:
+        eg, er = got.species[0], ref.species[0]
+        er.sort_by_id()
+        assert np.array_equal(eg.id, er.id)

@@ -22,6 +22,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(GridView g, SpeciesView e, do
     __syncthreads();
     const int n = e.count[sc];
     const int64_t base = (int64_t)sc * e.cap;
+#pragma unroll 4
     for (int t = tid; t < n; t += BLOCK) {
         const int64_t p = base + t;
         const int cell = (int)e.x[p] + SX * ((int)e.y[p] + SY * (int)e.z[p]);
@@ -67,31 +68,24 @@ __global__ __launch_bounds__(BLOCK) void k_rate_exact(GridView g, SpeciesView io
                                                       unsigned long long* counters)
 {
     __shared__ double glx[GL_NODES], glw[GL_NODES];
-    __shared__ int s_active;
     const int sc = blockIdx.x;
     const int tid = threadIdx.x;
     if (tid < GL_NODES) { glx[tid] = gl[tid]; glw[tid] = gl[GL_NODES + tid]; }
-    if (tid == 0) s_active = 0;
     __syncthreads();
     const int n = ion.count[sc];
     const int64_t base = (int64_t)sc * ion.cap;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
-    int active = 0;
     for (int t = tid; t < n; t += BLOCK) {
         const int64_t p = base + t;
         const int Z = ion.zs[p];
         double v = 0.0;
         if (Z < tab.z_max) {
-            ++active;
             const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
                                (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
             v = rate_exact(kT[gi], ne[gi], tab, Z, glx, glw);
         }
         nu[p] = v;
     }
-    atomicAdd(&s_active, active);
-    __syncthreads();
-    if (tid == 0 && s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
 }
 
 hipError_t launch_rate_exact(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
@@ -136,11 +130,12 @@ __device__ inline uint64_t word(const Philox4& r, int e)
 // event e adding -ln(1 - u_e) / nu_{Z+e} while the running time stays below
 // dt_phys; u_e is word e % 4 of the block of (id, species, 2, step) for e < 4
 // and of (id, species, 6, step) after; later events take the exact rate.
+template <bool CHAIN>
 __device__ inline int ion_events(const IonTables& tab, const DrawArgs& a, uint32_t id, int Z0, double nu0, double kT,
                                  double ne, const double* glx, const double* glw)
 {
     const Philox4 r = philox4x64_10((uint64_t)id, (uint64_t)a.species_index, PURPOSE_IONIZE, (uint64_t)a.step, a.seed, 0);
-    if (a.max_events <= 1) return u01(r.v[0]) < -expm1(-nu0 * a.dt_phys) ? 1 : 0;
+    if constexpr (!CHAIN) return u01(r.v[0]) < -expm1(-nu0 * a.dt_phys) ? 1 : 0;
     Philox4 r2{};
     double t = 0.0;
     int nev = 0;
@@ -157,22 +152,24 @@ __device__ inline int ion_events(const IonTables& tab, const DrawArgs& a, uint32
     return nev;
 }
 
-// Per ion with Z < z_max: its events, then one electron per event at the end
+// Per ion with Z < z_max (counted, striped, at CNT_ACTIVE): its events, then one electron per event at the end
 // of the same supercell's electron frames (one LDS atomic per ion with
 // events), position / momentum / weight of the ion, charge state raised by
 // the events that found a slot.  With energy loss, w * P_Z of those events
 // goes to the cell's de and the supercell's electron count before the
 // appends to old_count.
+// CHAIN: max_events > 1 (the instantiation for one event carries no quadrature).
+template <bool CHAIN>
 __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView ion, SpeciesView el, IonTables tab,
                                                        DrawArgs a, const double* nu, DrawBuffers db,
                                                        unsigned long long* counters)
 {
     __shared__ double glx[GL_NODES], glw[GL_NODES];
-    __shared__ int s_add, s_fired;
+    __shared__ int s_add, s_fired, s_active;
     const int sc = blockIdx.x;
     const int tid = threadIdx.x;
-    if (a.max_events > 1 && tid < GL_NODES) { glx[tid] = db.gl[tid]; glw[tid] = db.gl[GL_NODES + tid]; }
-    if (tid == 0) { s_add = 0; s_fired = 0; }
+    if (CHAIN && tid < GL_NODES) { glx[tid] = db.gl[tid]; glw[tid] = db.gl[GL_NODES + tid]; }
+    if (tid == 0) { s_add = 0; s_fired = 0; s_active = 0; }
     __syncthreads();
     const int n = ion.count[sc];
     const int ebase = el.count[sc];
@@ -181,20 +178,21 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
     const int64_t ebase64 = (int64_t)sc * el.cap;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     bool full = false;
-    int fired = 0;
+    int fired = 0, active = 0;
     for (int t = tid; t < n; t += BLOCK) {
         const int64_t p = base + t;
         const int Z0 = ion.zs[p];
         if (Z0 >= tab.z_max) continue;
+        ++active;
         // the ion's cell, for later events' rates and the energy account only
-        const bool need_cell = a.max_events > 1 || a.energy_loss;
+        const bool need_cell = CHAIN || a.energy_loss;
         const int64_t gi = need_cell ? (int64_t)(scx * SX + (int)ion.x[p]) +
                                            (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) +
                                                             (int64_t)g.ny * (scz * SZ + (int)ion.z[p]))
                                      : 0;
         const uint32_t id = ion.id[p];
-        const int nev = ion_events(tab, a, id, Z0, nu[p], a.max_events > 1 ? db.kT[gi] : 0.0,
-                                   a.max_events > 1 ? db.ne[gi] : 0.0, glx, glw);
+        const int nev = ion_events<CHAIN>(tab, a, id, Z0, nu[p], CHAIN ? db.kT[gi] : 0.0, CHAIN ? db.ne[gi] : 0.0,
+                                          glx, glw);
         if (nev == 0) continue;
         const int b = atomicAdd(&s_add, nev);
         int done = 0;
@@ -219,12 +217,14 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
     }
     if (full) g.flags[FLAG_CAPACITY] = 1;
     if (fired) atomicAdd(&s_fired, fired);
+    if (active) atomicAdd(&s_active, active);
     __syncthreads();
     if (tid == 0) {
+        if (s_active) atomicAdd(&counters[CNT_ACTIVE + sc % CNT_STRIPES], (unsigned long long)s_active);
         const int added = s_add < room ? s_add : room;
         el.count[sc] = ebase + added;
         if (a.energy_loss) db.old_count[sc] = ebase;
-        if (s_fired) atomicAdd(&counters[1], (unsigned long long)s_fired);
+        if (s_fired) atomicAdd(&counters[CNT_FIRED + sc % CNT_STRIPES], (unsigned long long)s_fired);
     }
 }
 
@@ -233,7 +233,10 @@ hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const S
                               hipStream_t st)
 {
     if (a.energy_loss && (!b.de || !b.old_count || !b.mom4)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_draw_append, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, nu, b, counters);
+    if (a.max_events > 1)
+        hipLaunchKernelGGL(k_draw_append<true>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, nu, b, counters);
+    else
+        hipLaunchKernelGGL(k_draw_append<false>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, nu, b, counters);
     return hipGetLastError();
 }
 

@@ -230,9 +230,9 @@ struct MlpArgs {
 
 // Per supercell of ions: nu[p] for every ion (0 for Z >= z_max).  Ions whose
 // inputs lie outside the trained range are appended to `fb_list` (their
-// count in counters[2]) and take the exact FP64 quadrature in a second,
+// count in counters[CNT_FALLBACK]) and take the exact FP64 quadrature in a second,
 // small kernel, so that the quadrature's registers do not lower this
-// kernel's occupancy.  counters[0] += active ions.  Persistent workgroups
+// kernel's occupancy.  Persistent workgroups
 // (weights loaded once); a wave takes 64 ions of a supercell at a time, one
 // per lane.
 __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion, IonTables tab, MlpArgs m,
@@ -240,14 +240,11 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
                                                     unsigned long long* counters, unsigned long long* fb_list)
 {
     __shared__ PriorTab PT;
-    __shared__ int s_active;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     fill_prior(tab, PT);
-    if (tid == 0) s_active = 0;
     Net net;
     load_net(m.params, lane, net);
     __syncthreads();
-    int active = 0;
     for (int sc = blockIdx.x; sc < g.nsc; sc += gridDim.x) {
         const int n = ion.count[sc];
         const int64_t base = (int64_t)sc * ion.cap;
@@ -275,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
             if (fmask) {  // wave-uniform; rare
                 const int leader = __ffsll((long long)fmask) - 1;
                 unsigned long long fbase = 0;
-                if (lane == leader) fbase = atomicAdd(&counters[2], (unsigned long long)__popcll(fmask));
+                if (lane == leader) fbase = atomicAdd(&counters[CNT_FALLBACK], (unsigned long long)__popcll(fmask));
                 fbase = __shfl(fbase, leader, 64);
                 if (fb)
                     fb_list[fbase + (unsigned)__builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32),
@@ -283,15 +280,11 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
                         (unsigned long long)p;
             }
             if (t < n) {
-                active += act ? 1 : 0;
                 // ln nu <= ~40 on the trained range; fallback ions are written by the second kernel
                 nu[p] = inr ? (double)__expf(prior + m.mu + m.s * y) : 0.0;
             }
         }
     }
-    atomicAdd(&s_active, active);
-    __syncthreads();
-    if (tid == 0 && s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
 }
 
 // The exact FP64 rate for the ions listed by k_rate_mlp.
@@ -303,7 +296,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_fallback(GridView g, SpeciesView
     __shared__ double glx[GL_NODES], glw[GL_NODES];
     if (threadIdx.x < GL_NODES) { glx[threadIdx.x] = gl[threadIdx.x]; glw[threadIdx.x] = gl[GL_NODES + threadIdx.x]; }
     __syncthreads();
-    const unsigned long long cnt = counters[2];
+    const unsigned long long cnt = counters[CNT_FALLBACK];
     for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < cnt;
          i += (unsigned long long)gridDim.x * BLOCK) {
         const int64_t p = (int64_t)fb_list[i];

@@ -67,30 +67,29 @@ __device__ inline bool rate_from_table(double kT, double ne, const IonTables& ta
     return true;
 }
 
-// Per ion with Z < z_max, like the exact rate kernel.  Ions whose cell lies
-// outside the table's kT range are appended to fb_list (their count in
-// counters[2]) and take the exact quadrature in the fallback kernel.
+// One thread per ion slot: blockIdx.x the supercell, blockIdx.y the chunk of
+// BLOCK slots (many short blocks keep enough loads in flight).  Ions whose
+// cell lies outside the table's kT range are appended to fb_list (their
+// count in counters[CNT_FALLBACK]) and take the exact quadrature in the fallback kernel.
 __global__ __launch_bounds__(BLOCK) void k_rate_table(GridView g, SpeciesView ion, IonTables tab, const double* ne,
                                                       const double* kT, double* nu, const double* table,
                                                       unsigned long long* counters, unsigned long long* fb_list)
 {
-    __shared__ int s_active;
     const int sc = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid == 0) s_active = 0;
-    __syncthreads();
     const int n = ion.count[sc];
+    const int t0 = blockIdx.y * BLOCK;
+    if (t0 >= n) return;  // block-uniform
     const int64_t base = (int64_t)sc * ion.cap;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
-    int active = 0;
-    for (int t = tid; t - lane < n; t += BLOCK) {  // wave-uniform trip count
+    {
+        const int t = t0 + tid;
         const int64_t p = base + t;
         bool fb = false;
         if (t < n) {
             const int Z = ion.zs[p];
             double v = 0.0;
             if (Z < tab.z_max) {
-                ++active;
                 const int64_t gi = (int64_t)(scx * SX + (int)ion.x[p]) +
                                    (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
                 const double t_ev = kT[gi], n_cm3 = ne[gi];
@@ -102,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_table(GridView g, SpeciesView io
         if (fmask) {  // rare
             const int leader = __ffsll((long long)fmask) - 1;
             unsigned long long fbase = 0;
-            if (lane == leader) fbase = atomicAdd(&counters[2], (unsigned long long)__popcll(fmask));
+            if (lane == leader) fbase = atomicAdd(&counters[CNT_FALLBACK], (unsigned long long)__popcll(fmask));
             fbase = __shfl(fbase, leader, 64);
             if (fb)
                 fb_list[fbase + (unsigned)__builtin_amdgcn_mbcnt_hi((unsigned)(fmask >> 32),
@@ -110,16 +109,14 @@ __global__ __launch_bounds__(BLOCK) void k_rate_table(GridView g, SpeciesView io
                     (unsigned long long)p;
         }
     }
-    if (active) atomicAdd(&s_active, active);
-    __syncthreads();
-    if (tid == 0 && s_active) atomicAdd(&counters[0], (unsigned long long)s_active);
 }
 
 hipError_t launch_rate_table(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
                              const double* kT, double* nu, const double* table, const double* gl,
                              unsigned long long* counters, unsigned long long* fb_list, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rate_table, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, table, counters, fb_list);
+    const dim3 grid(g.nsc, (ion.cap + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_rate_table, grid, dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, table, counters, fb_list);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_rate_fallback(g, ion, tab, ne, kT, nu, gl, fb_list, counters, st);

@@ -51,7 +51,7 @@ struct pic_ctx {
     double* rtab[PIC_MAX_SPECIES] = {};      // tabulated subshell sums (PIC_RATE_TABLE), built at first use
     bool rtab_ready[PIC_MAX_SPECIES] = {};
     unsigned long long* fbl[PIC_MAX_SPECIES] = {};  // per ion slot: surrogate fallback list
-    unsigned long long* counters = nullptr;  // active, ionised, fallback
+    unsigned long long* counters = nullptr;  // CNT_WORDS ionisation counters (fallback list, striped active / ionised)
     hipEvent_t iev[4] = {};
     // surrogate per ion species
     struct Mlp {
@@ -290,7 +290,7 @@ int alloc_ionisation(pic_ctx* c)
     if (!any) return PIC_OK;
     const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
     if (!(c->gl = (double*)dev_alloc(c, 2 * GL_NODES * 8)) || !(c->ne = (double*)dev_alloc(c, N * 8)) ||
-        !(c->kT = (double*)dev_alloc(c, N * 8)) || !(c->counters = (unsigned long long*)dev_alloc(c, 64)))
+        !(c->kT = (double*)dev_alloc(c, N * 8)) || !(c->counters = (unsigned long long*)dev_alloc(c, CNT_WORDS * 8)))
         return fail(c, PIC_ERR_OOM, "device allocation of ionisation buffers failed");
     for (int s = 0; s < c->nsp; ++s) {
         if (c->sp[s].desc.z_max == 0) continue;
@@ -969,7 +969,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         if (!ionising(c, s)) continue;
         const int e = c->sp[s].desc.ionize_into;
         const IonTables tab = ion_tables(c, s);
-        HIPCHK(c, launch_zero_i32((int32_t*)c->counters, 8, c->stream));
+        HIPCHK(c, launch_zero_i32((int32_t*)c->counters, 2 * CNT_WORDS, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[0], c->stream));
         const pic_species_t& d = c->sp[s].desc;
         const bool eloss = d.energy_loss != 0;
@@ -1000,7 +1000,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], db, c->counters, c->stream));
         if (eloss) HIPCHK(c, launch_energy_loss(c->g, c->sp[e].v, db, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[3], c->stream));
-        unsigned long long cnt[4];
+        unsigned long long cnt[CNT_WORDS];
         HIPCHK(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         float r = 0.f, t = 0.f;
@@ -1008,9 +1008,11 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         HIPCHK(c, hipEventElapsedTime(&t, c->iev[0], c->iev[3]));
         rate_ms += r;
         total_ms += t;
-        st.ions_active += (int64_t)cnt[0];
-        st.ionized += (int64_t)cnt[1];
-        st.fallback += (int64_t)cnt[2];
+        for (int k = 0; k < CNT_STRIPES; ++k) {
+            st.ions_active += (int64_t)cnt[CNT_ACTIVE + k];
+            st.ionized += (int64_t)cnt[CNT_FIRED + k];
+        }
+        st.fallback += (int64_t)cnt[CNT_FALLBACK];
         std::vector<int32_t> cc;
         st.electrons = host_count(c, e, cc);
         c->sp[e].wmax = std::max(c->sp[e].wmax, c->sp[s].wmax);  // born electrons carry ion weights

@@ -158,6 +158,13 @@ struct IonTables {
     int z_max;
 };
 
+// Ionisation counters (unsigned long long): [CNT_FALLBACK] is the length of
+// the fallback list; the active-ion and event counts are striped over
+// CNT_STRIPES words each (supercell sc adds to word sc % CNT_STRIPES) so that
+// thousands of workgroups do not serialise on one address; the host sums them.
+constexpr int CNT_FALLBACK = 2, CNT_STRIPES = 64;
+constexpr int CNT_ACTIVE = 8, CNT_FIRED = CNT_ACTIVE + CNT_STRIPES, CNT_WORDS = CNT_FIRED + CNT_STRIPES;
+
 struct DrawArgs {
     uint64_t seed;
     int64_t step;

@@ -118,6 +118,54 @@ def copy_calibration() -> int:
     return 0
 
 
+def _counter_rows(run_dir: str):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def counter_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str) -> int:
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the default
+    benchmark, then of --copy-calibration) into the counter summary that
+    roofline.traffic is computed from, stamped with the particle kernel's
+    source hash."""
+    push = "k_push<1, false, false, 256, float>"
+
+    def push_avg(run_dir, counter):
+        v = [float(r["Counter_Value"]) for r in _counter_rows(run_dir)
+             if push in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        if not v:
+            raise SystemExit(f"no {counter} rows for {push} under {run_dir}")
+        return sum(v) / len(v), len(v)
+
+    def copy_max(run_dir, counter):
+        v = [float(r["Counter_Value"]) for r in _counter_rows(run_dir)
+             if "copy" in r["Kernel_Name"].lower() and r["Counter_Name"] == counter]
+        if not v:
+            raise SystemExit(f"no {counter} rows for a copy kernel under {run_dir}")
+        return max(v)
+
+    fetch, nd = push_avg(fetch_dir, "FETCH_SIZE")
+    write, _ = push_avg(write_dir, "WRITE_SIZE")
+    cf, cw = copy_max(copy_fetch_dir, "FETCH_SIZE"), copy_max(copy_write_dir, "WRITE_SIZE")
+    cfg = workloads.config(1)
+    gc = cfg["grid"]
+    d = {"k_push_sha256_16": source_hash(PUSH_SOURCES),
+         "particles": gc["nx"] * gc["ny"] * gc["nz"] * cfg["species"][0]["ppc"],
+         "workload": cfg["workload"],
+         "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1), "dispatches": nd,
+         "fetch_scale": round(cf / 1048576.0, 4), "write_scale": round(cw / 1048576.0, 4),
+         "copy_fetch_kib_per_gib": round(cf, 1), "copy_write_kib_per_gib": round(cw, 1)}
+    with open(PROFILE_COUNTERS, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d), flush=True)
+    return 0
+
+
 def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     """Monte Carlo ionisation on the 128^3 electron-carbon workload: GPU time
     of the rate stage and of the whole step with the exact FP64 GL-64
@@ -210,9 +258,13 @@ def main(argv=None):
                     help="the FP64 variant of the PIC cycle (the ionisation leg, FP32 only, is skipped)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the counter summary behind roofline.traffic from four rocprofv3 --pmc runs")
     args = ap.parse_args(argv)
     if args.copy_calibration:
         return copy_calibration()
+    if args.counter_summary:
+        return counter_summary(*args.counter_summary)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

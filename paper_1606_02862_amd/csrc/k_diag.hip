@@ -159,15 +159,25 @@ __device__ inline void rho_weights(double x, int* first, double* w)
     }
 }
 
+// Charge density in FP64: each workgroup deposits its supercell's particles
+// into an LDS tile of nodes [-1, S+1] per axis (every shape's support from a
+// particle inside the supercell lies there) with native FP64 LDS atomics,
+// then adds the tile to rho with one global FP64 atomic per node.
+constexpr int RHO_TX = SX + 3, RHO_TY = SY + 3, RHO_TZ = SZ + 3, RHO_TN = RHO_TX * RHO_TY * RHO_TZ;
+
 template <int ORDER, class R>
 __global__ __launch_bounds__(BLOCK) void k_rho(GridViewT<R> g, SpeciesViewT<R> s, double* rho)
 {
+    __shared__ double tile[RHO_TN];
     const int sc = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < RHO_TN; t += BLOCK) tile[t] = 0.0;
+    __syncthreads();
     const int n = s.count[sc];
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     const int64_t base = (int64_t)sc * s.cap;
     const double inv_dv = 1.0 / ((double)g.dx * g.dy * g.dz);
-    for (int t = threadIdx.x; t < n; t += BLOCK) {
+    for (int t = tid; t < n; t += BLOCK) {
         const int64_t p = base + t;
         double q = s.charge;
         if (s.zs) q *= (double)s.zs[p];
@@ -177,19 +187,28 @@ __global__ __launch_bounds__(BLOCK) void k_rho(GridViewT<R> g, SpeciesViewT<R> s
         rho_weights<ORDER>((double)s.x[p], &fx, wx);
         rho_weights<ORDER>((double)s.y[p], &fy, wy);
         rho_weights<ORDER>((double)s.z[p], &fz, wz);
-        for (int c = 0; c <= ORDER; ++c) {
-            int gz = scz * SZ + fz + c;
-            gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
+        // a particle inside its supercell always passes; anything else is skipped
+        if (fx < -1 || fx > SX + 1 - ORDER || fy < -1 || fy > SY + 1 - ORDER || fz < -1 || fz > SZ + 1 - ORDER) continue;
+#pragma unroll
+        for (int c = 0; c <= ORDER; ++c)
+#pragma unroll
             for (int b = 0; b <= ORDER; ++b) {
-                int gy = scy * SY + fy + b;
-                gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
-                for (int a = 0; a <= ORDER; ++a) {
-                    int gx = scx * SX + fx + a;
-                    gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
-                    unsafeAtomicAdd(&rho[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz)], qw * wx[a] * wy[b] * wz[c]);
-                }
+                const int row = ((fz + c + 1) * RHO_TY + (fy + b + 1)) * RHO_TX + (fx + 1);
+                const double wyz = qw * wy[b] * wz[c];
+#pragma unroll
+                for (int a = 0; a <= ORDER; ++a) atomicAdd(&tile[row + a], wyz * wx[a]);
             }
-        }
+    }
+    __syncthreads();
+    for (int t = tid; t < RHO_TN; t += BLOCK) {
+        const double v = tile[t];
+        if (v == 0.0) continue;
+        const int tx = t % RHO_TX, ty = (t / RHO_TX) % RHO_TY, tz = t / (RHO_TX * RHO_TY);
+        int gx = scx * SX + tx - 1, gy = scy * SY + ty - 1, gz = scz * SZ + tz - 1;
+        gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
+        gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
+        gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
+        unsafeAtomicAdd(&rho[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz)], v);
     }
 }
 

@@ -88,10 +88,11 @@ def host_description():
     return cpu, os.cpu_count()
 
 
-def cpu_baseline(cfg_idx: int, box: int, steps: int) -> dict:
-    """The FP64 oracle (plain C, one thread) on a sub-box of the same workload."""
+def cpu_baseline(cfg_idx: int, box: int, steps: int, **grid) -> dict:
+    """The FP64 oracle (plain C, one thread) on a sub-box of the same workload
+    (grid: the same shape / gather overrides as the GPU run)."""
     import oracle
-    cfg = workloads.config(cfg_idx, nx=box, ny=box, nz=box)
+    cfg = workloads.config(cfg_idx, nx=box, ny=box, nz=box, **grid)
     st = oracle.init_state(cfg)
     n = sum(s.n for s in st.species if s.mobile)
     t0 = time.perf_counter()
@@ -254,6 +255,8 @@ def main(argv=None):
     ap.add_argument("--cpu-box", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-ionize", action="store_true", help="skip the ionisation leg")
+    ap.add_argument("--shape", choices=("cic", "tsc", "pcs"), help="override the workload's particle shape")
+    ap.add_argument("--gather", choices=("standard", "galerkin"), help="override the field gather")
     ap.add_argument("--fp64", action="store_true",
                     help="the FP64 variant of the PIC cycle (the ionisation leg, FP32 only, is skipped)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -282,6 +285,12 @@ def main(argv=None):
     cfg = workloads.config(args.config)
     if args.fp64:
         cfg["grid"]["precision"] = "fp64"
+    overridden = False
+    for key in ("shape", "gather"):
+        if getattr(args, key) and getattr(args, key) != cfg["grid"].get(key, "standard"):
+            cfg["grid"][key] = getattr(args, key)
+            cfg["workload"] += f", {key} {getattr(args, key)}"
+            overridden = True
     es = 8 if args.fp64 else 4
     gc = cfg["grid"]
     ncell = gc["nx"] * gc["ny"] * gc["nz"]
@@ -315,7 +324,8 @@ def main(argv=None):
     per_launch = algorithmic_bytes_per_push(n_particles // max(1, sum(1 for s in cfg["species"] if s["mobile"])),
                                             ncell, order, es)
     achieved = per_launch / (push_avg_ms * 1e-3) / 1e9
-    traffic = None if args.fp64 else traffic_from_profile(n_particles)
+    # the counter summary covers the default FP32 workload only
+    traffic = None if (args.fp64 or overridden or args.config != 1) else traffic_from_profile(n_particles)
     step_bytes = algorithmic_bytes_per_step(n_particles, ncell, es)
     value = n_particles * args.steps / (ms * 1e-3)
     line = {
@@ -332,6 +342,7 @@ def main(argv=None):
         "dtype": "f64" if args.fp64 else "f32",
         "data": "synthetic (seeded Philox initial state generated on the GPU)",
         "config": {"workload": cfg["workload"], "grid": [gc["nx"], gc["ny"], gc["nz"]], "shape": gc["shape"],
+                   "gather": gc.get("gather", "standard"),
                    "species": [{"name": s["name"], "ppc": s["ppc"], "mass": s["mass"]} for s in cfg["species"]],
                    "particles": n_particles, "supercell": [8, 8, 4], "dt": gc["dt"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -347,7 +358,8 @@ def main(argv=None):
     if not args.no_ionize and not args.fp64:
         line["ionize"] = ionize_leg(P, torch, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps)
+        over = {k: getattr(args, k) for k in ("shape", "gather") if getattr(args, k)}
+        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps, **over)
     print(json.dumps(line), flush=True)
     return 0
 

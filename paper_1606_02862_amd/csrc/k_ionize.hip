@@ -64,8 +64,7 @@ hipError_t launch_moments(const GridView& g, const SpeciesView& e, double n_ref_
 
 // ---------------------------------------------------------------- exact rate
 __global__ __launch_bounds__(BLOCK) void k_rate_exact(GridView g, SpeciesView ion, IonTables tab, const double* ne,
-                                                      const double* kT, double* nu, const double* gl,
-                                                      unsigned long long* counters)
+                                                      const double* kT, double* nu, const double* gl)
 {
     __shared__ double glx[GL_NODES], glw[GL_NODES];
     const int sc = blockIdx.x;
@@ -89,10 +88,9 @@ __global__ __launch_bounds__(BLOCK) void k_rate_exact(GridView g, SpeciesView io
 }
 
 hipError_t launch_rate_exact(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
-                             const double* kT, double* nu, const double* gl, unsigned long long* counters,
-                             hipStream_t st)
+                             const double* kT, double* nu, const double* gl, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rate_exact, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, gl, counters);
+    hipLaunchKernelGGL(k_rate_exact, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, tab, ne, kT, nu, gl);
     return hipGetLastError();
 }
 

@@ -978,7 +978,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         if (eloss) HIPCHK(c, launch_zero_f64(c->de, (int64_t)c->grid.nx * c->grid.ny * c->grid.nz, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
         if (mode == PIC_RATE_EXACT)
-            HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->counters, c->stream));
+            HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->stream));
         else if (mode == PIC_RATE_TABLE)
             HIPCHK(c, launch_rate_table(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->rtab[s], c->gl, c->counters,
                                         c->fbl[s], c->stream));

@@ -204,8 +204,7 @@ const double* gauss_laguerre_nodes(const double** w);
 hipError_t launch_moments(const GridView& g, const SpeciesView& e, double n_ref_over_dv, double* ne, double* kT,
                           double* mom4, hipStream_t st);
 hipError_t launch_rate_exact(const GridView& g, const SpeciesView& ion, const IonTables& tab, const double* ne,
-                             const double* kT, double* nu, const double* gl, unsigned long long* counters,
-                             hipStream_t st);
+                             const double* kT, double* nu, const double* gl, hipStream_t st);
 hipError_t launch_ln_rate_exact(int64_t n, const double* kT, const double* ne, const int32_t* Z, const IonTables& tab,
                                 const double* gl, double* out, hipStream_t st);
 hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,

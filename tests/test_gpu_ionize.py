@@ -314,3 +314,71 @@ def test_ionize_mlp_with_every_ion_out_of_range_equals_exact(trained, P):
     assert np.array_equal(ions_e["zstate"], ions_m["zstate"])
     for k in ("id", "x", "y", "z", "ux", "uy", "uz", "w"):
         assert np.array_equal(el_e[k], el_m[k]), k
+
+
+# ---------------------------------------------------------------------------
+# full size: the benchmark's ionisation workload
+
+def test_full_size_carbon_ionize_sampled_parity(P):
+    """128^3, 8 electrons + 4 C2+ per cell (25M particles), exact rates, the
+    launch configuration the benchmark times: cell moments of every cell from
+    the oracle over all electrons pulled from the GPU; for a sample of ions,
+    the oracle's GL-64 rate, Philox draw and decision against the GPU's new
+    charge state; every sampled event's electron sits on its ion."""
+    from types import SimpleNamespace
+    cfg = workloads.config(3)
+    gc = cfg["grid"]
+    ncell = gc["nx"] * gc["ny"] * gc["nz"]
+    n_e0, n_c0 = ncell * 8, ncell * 4
+    _print("full-size 128^3 carbon ionisation sampled parity")
+    with P.Pic(cfg) as pic:
+        pic.step(2)
+        el = pic.get_particles(0)
+        ion = pic.get_particles(1)
+        ne_g, kT_g = pic.cell_moments(1)
+        stats = pic.ionize("exact")
+        ion2 = pic.get_particles(1)
+        el2 = pic.get_particles(0)
+    g = oracle.grid_from_config(cfg)
+    st = SimpleNamespace(grid=g, species=[SimpleNamespace(**{k: el[k].astype(np.float64)
+                                                             for k in ("x", "y", "z", "ux", "uy", "uz", "w")})])
+    ne_r, kT_r = ionize.density_temperature(ionize.cell_moments(st, 0), g.dx * g.dy * g.dz, gc["n_ref_cm3"])
+    assert np.max(np.abs(ne_g / ne_r - 1)) < 1e-12
+    assert np.max(np.abs(kT_g - kT_r) / kT_r) < 1e-10
+    # sampled ions: GPU decision against the oracle's
+    o1, o2 = np.argsort(ion["id"]), np.argsort(ion2["id"])
+    assert np.array_equal(ion["id"][o1], ion2["id"][o2])
+    k = workloads.rng(91).choice(n_c0, 20000, replace=False)
+    ids = ion["id"][o1][k]
+    Z0 = ion["zstate"][o1][k]
+    Z1 = ion2["zstate"][o2][k]
+    x, y, z = (ion[c][o1][k] for c in ("x", "y", "z"))
+    cell = ((np.floor(x).astype(np.int64) % g.nx) + g.nx * ((np.floor(y).astype(np.int64) % g.ny)
+                                                           + g.ny * (np.floor(z).astype(np.int64) % g.nz)))
+    sh = ionize.lotz_shells(cfg["species"][1])
+    nu = np.zeros(k.size)
+    for zz in np.unique(Z0):
+        m = Z0 == zz
+        nu[m] = ionize.rate_shells(kT_r[cell[m]], ne_r[cell[m]], sh[int(zz)])
+    p = -np.expm1(-nu * gc["dt"] / ionize.omega_p(gc["n_ref_cm3"]))
+    u = ionize.ion_uniforms(gc["seed"], ids, 1, 2)
+    want = (u < p).astype(np.int64)
+    got = (Z1 - Z0).astype(np.int64)
+    _print("sampled ions", k.size, "events ref/gpu", int(want.sum()), int(got.sum()), "all events", stats["ionized"])
+    assert stats["ions_active"] == n_c0 and stats["ionized"] > 1000
+    differ = np.nonzero(got != want)[0]
+    assert len(differ) <= 1
+    for i in differ:
+        assert abs(u[i] - p[i]) < 1e-12 * p[i]
+    # electrons of the sampled events, on their ions
+    fired = np.nonzero(got == 1)[0]
+    assert fired.size > 0
+    new_ids = n_e0 + n_c0 + (ids[fired] - n_e0) * cfg["species"][1]["z_max"] + Z0[fired]
+    order = np.argsort(el2["id"])
+    sid = el2["id"][order]
+    at = np.searchsorted(sid, new_ids)
+    assert np.array_equal(sid[at], new_ids)
+    q = order[at]
+    assert np.array_equal(el2["x"][q], x[fired]) and np.array_equal(el2["y"][q], y[fired])
+    assert np.array_equal(el2["z"][q], z[fired])
+    assert el2["id"].size == n_e0 + stats["ionized"]

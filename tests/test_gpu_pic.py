@@ -338,25 +338,32 @@ def test_full_size_shear128_sampled_parity(P):
     assert m["gauss_max"] <= 1e-4 * m["rho_max"]
 
 
-def test_full_size_ep256_tsc_sampled_parity(P):
-    """256x256x128 TSC, electrons + protons at 8 ppc each in B0 (134M
-    particles): sampled momenta and positions of both species against the
-    oracle's gather, Boris and move from the GPU's own pre-step state; Gauss
-    and particle counts over the run."""
-    cfg = workloads.config(2)
-    _print("full-size 256x256x128 TSC sampled parity")
+@pytest.mark.parametrize("idx,gather", [
+    (2, "standard"),   # 256x256x128 TSC, electrons + protons at 8 ppc each in B0 (134M particles)
+    (5, "standard"),   # 128^3 TSC Kelvin-Helmholtz shear flow, electrons + protons at 16 ppc each (67M)
+    (1, "galerkin"),   # 128^3 CIC shear layer (33.6M electrons) with the Galerkin gather
+])
+def test_full_size_sampled_parity(P, idx, gather):
+    """Full-size workloads in the benchmark's launch configuration: sampled
+    momenta and positions of every species against the oracle's gather, Boris
+    and move from the GPU's own pre-step state; Gauss and particle counts over
+    the run."""
+    cfg = workloads.config(idx, gather=gather)
+    gc = cfg["grid"]
+    nx, ny, nz = gc["nx"], gc["ny"], gc["nz"]
+    nsp = len(cfg["species"])
+    _print("full-size sampled parity", cfg["workload"], gather)
     g = oracle.grid_from_config(cfg)
-    nx, ny, nz = 256, 256, 128
     with P.Pic(cfg) as pic:
         pic.step(3)
         E, B, _ = pic.get_fields()
-        pre = [pic.get_particles(i) for i in range(2)]
+        pre = [pic.get_particles(i) for i in range(nsp)]
         rng = workloads.rng(78)
-        idx = [rng.choice(p["id"].size, 1500, replace=False) for p in pre]
-        pre = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(pre, idx)]
+        sel = [rng.choice(p["id"].size, 1500, replace=False) for p in pre]
+        pre = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(pre, sel)]
         pic.step(1)
-        post = [pic.get_particles(i) for i in range(2)]
-        post = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(post, idx)]
+        post = [pic.get_particles(i) for i in range(nsp)]
+        post = [{k: p[k][i] for k in ("x", "y", "z", "ux", "uy", "uz", "id")} for p, i in zip(post, sel)]
         m = pic.moments()
     E, B = E.astype(np.float64), B.astype(np.float64)
     for sp, a, b in zip(cfg["species"], pre, post):
@@ -374,7 +381,7 @@ def test_full_size_ep256_tsc_sampled_parity(P):
         _print(sp["name"], "sampled momentum error", eu, "position error", ex)
         assert eu <= 1e-5 and ex <= 4e-6
     _print("gauss", m["gauss_max"], m["rho_max"], "counts", m["count"])
-    assert list(m["count"]) == [nx * ny * nz * 8, nx * ny * nz * 8]
+    assert list(m["count"])[:nsp] == [nx * ny * nz * sp["ppc"] for sp in cfg["species"]]
     assert m["gauss_max"] <= 1e-4 * m["rho_max"]
 
 

@@ -150,12 +150,12 @@ __device__ inline int ion_events(const IonTables& tab, const DrawArgs& a, uint32
     return nev;
 }
 
-// Per ion with Z < z_max (counted, striped, at CNT_ACTIVE): its events, then one electron per event at the end
-// of the same supercell's electron frames (one LDS atomic per ion with
-// events), position / momentum / weight of the ion, charge state raised by
-// the events that found a slot.  With energy loss, w * P_Z of those events
-// goes to the cell's de and the supercell's electron count before the
-// appends to old_count.
+// Per ion with Z < z_max (counted, striped, at CNT_ACTIVE): its events, then
+// one electron per event at the end of the same supercell's electron frames
+// (one LDS atomic per ion with events), with the position, momentum and
+// weight of the ion; the charge state rises by the events that found a slot.
+// With energy loss, w * P_Z of those events goes to the cell's de and the
+// supercell's electron count before the appends to old_count.
 // CHAIN: max_events > 1 (the instantiation for one event carries no quadrature).
 template <bool CHAIN>
 __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView ion, SpeciesView el, IonTables tab,

@@ -107,6 +107,44 @@ def test_one_step_parity_pcs(P, idx, box, warm):
     assert err["E"] <= 1e-4 and err["B"] <= 1e-4
 
 
+def _face_positions(x, n, r):
+    """Move about half of the coordinates onto cell faces, cell centres and the
+    FP32 neighbours of faces (supercell faces included), all in [0, n)."""
+    k = np.arange(n, dtype=np.float32)
+    cand = np.concatenate([k, k + np.float32(0.5),
+                           np.nextafter(k + np.float32(1), np.float32(0)),   # largest float below each face
+                           np.nextafter(k, np.float32(n))]).astype(np.float64)
+    pick = r.random(x.size) < 0.5
+    out = x.copy()
+    out[pick] = cand[r.integers(0, cand.size, int(pick.sum()))]
+    return out
+
+
+@pytest.mark.parametrize("shape", ["cic", "tsc", "pcs"])
+def test_one_step_parity_particles_on_faces(P, shape):
+    """Degenerate positions: particles exactly on cell and supercell faces, at
+    cell centres (the staggered weights' ties) and one FP32 step either side
+    of a face, with non-zero fields; the same bars as the other one-step
+    tests."""
+    cfg = workloads.config(2, nx=16, ny=16, nz=8, shape=shape)
+    st = _s0(cfg, 6)
+    r = workloads.rng(61)
+    for sp in st.species:
+        sp.x = _face_positions(sp.x, 16, r)
+        sp.y = _face_positions(sp.y, 16, r)
+        sp.z = _face_positions(sp.z, 8, r)
+    _print("one-step parity, particles on faces", shape)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print(err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-5
+    assert err["J"] <= 1e-4
+    assert max(err["x"]) <= 2e-6
+    assert err["E"] <= 1e-4 and err["B"] <= 1e-4
+
+
 @pytest.mark.parametrize("shape", ["cic", "tsc", "pcs"])
 def test_one_step_parity_galerkin(P, shape):
     """The Galerkin gather: each component's shape one order lower along the

@@ -2,7 +2,7 @@
 // exact Maxwellian-averaged Lotz rate by 64-point Gauss-Laguerre quadrature
 // in FP64, the Philox draw per ion and the append of the new electrons to
 // the ion's own supercell.
-#include "pic_device.hpp"
+#include "ionize_internal.hpp"
 
 namespace pic {
 

@@ -16,7 +16,7 @@
 // 16x16x32 over the hidden units), the small layers on VALU; gradients are
 // summed per wave in registers / LDS and added to a global accumulator once
 // per wave; Adam updates FP32 master weights.
-#include "pic_device.hpp"
+#include "ionize_internal.hpp"
 
 namespace pic {
 

@@ -6,7 +6,7 @@
 // factor e^{-P_Z/kT} and the vbar / kT prefactor stay analytic, so the table
 // holds a slowly varying function; outside [RATE_TABLE_TMIN, RATE_TABLE_TMAX]
 // the exact quadrature is used.
-#include "pic_device.hpp"
+#include "ionize_internal.hpp"
 
 namespace pic {
 

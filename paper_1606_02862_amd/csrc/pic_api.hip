@@ -13,7 +13,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "pic_internal.hpp"
+#include "ionize_internal.hpp"
 
 using namespace pic;
 

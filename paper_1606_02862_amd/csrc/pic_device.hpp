@@ -1,5 +1,6 @@
 // Device-side helpers shared by the kernels: the Philox4x64-10 generator and
-// the CIC / TSC assignment weights.
+// its counter layout, the real-type helpers, and the B-spline assignment
+// weights from NGP (order 0) to PCS (order 3).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -109,56 +110,6 @@ __device__ inline int shape_weights(R x, R* w)
         w[3] = sixth * d * d * d;
         return (int)f - 1;
     }
-}
-
-// ---------------------------------------------------------------- Lotz rate
-// One subshell (p, a, b, c, q) with E = p + kT x:
-//   <sigma v>_j = vbar (a q / (p kT)) e^{-p/kT} sum_k w_k ln(1 + x_k r) (1 - b e^{-c x_k r}),  r = kT / p,
-// FP64; the exponential only where b != 0.
-__device__ inline double lotz_sum(double r, double b, double c, const double* glx, const double* glw)
-{
-    double s = 0.0;
-    if (b == 0.0) {
-#pragma unroll 8
-        for (int k = 0; k < GL_NODES; ++k) s = fma(glw[k], log1p(glx[k] * r), s);
-    } else {
-#pragma unroll 4
-        for (int k = 0; k < GL_NODES; ++k) {
-            const double xr = glx[k] * r;
-            s = fma(glw[k] * log1p(xr), 1.0 - b * exp(-c * xr), s);
-        }
-    }
-    return s;
-}
-
-// sum_j (a_j q_j / p_j) e^{-(p_j - P)/kT} S_j over the subshells of state Z, P = P[Z]:
-// the state's <sigma v> is vbar / kT e^{-P/kT} times this.
-__device__ inline double lotz_shells(double kT, const IonTables& t, int Z, const double* glx, const double* glw)
-{
-    double acc = 0.0;
-    for (int j = 0; j < t.ns[Z]; ++j) {
-        const double p = t.sp[Z][j];
-        double v = t.aq[Z][j] / p * lotz_sum(kT / p, t.sb[Z][j], t.sc[Z][j], glx, glw);
-        if (j > 0) v *= exp(-(p - t.P[Z]) / kT);
-        acc += v;
-    }
-    return acc;
-}
-
-__device__ inline double vbar_cm_s(double kT) { return C_CM_S * sqrt(8.0 * kT / (M_PI * ME_C2_EV)); }
-
-__device__ inline double rate_exact(double kT, double ne, const IonTables& t, int Z, const double* glx,
-                                    const double* glw)
-{
-    if (!(kT > 0.0) || !(ne > 0.0)) return 0.0;
-    return ne * vbar_cm_s(kT) / kT * exp(-t.P[Z] / kT) * lotz_shells(kT, t, Z, glx, glw);
-}
-
-__device__ inline double ln_rate_exact(double kT, double ne, const IonTables& t, int Z, const double* glx,
-                                       const double* glw)
-{
-    if (!(kT > 0.0) || !(ne > 0.0)) return -INFINITY;
-    return log(ne * vbar_cm_s(kT) / kT) - t.P[Z] / kT + log(lotz_shells(kT, t, Z, glx, glw));
 }
 
 }  // namespace pic

@@ -12,7 +12,7 @@
 #include <cmath>
 #include <mutex>
 
-#include "pic_internal.hpp"
+#include "ionize_internal.hpp"
 
 namespace pic {
 namespace {

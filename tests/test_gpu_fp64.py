@@ -114,6 +114,30 @@ def test_fp64_one_step_parity_galerkin(P, shape):
     assert max(err["u"]) <= 1e-12 and max(err["x"]) <= 1e-12 and err["J"] <= 1e-12
 
 
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_fp64_one_step_parity_particles_on_faces(P, shape):
+    """Particles on cell and supercell faces, at cell centres and one FP64
+    step either side of a face (degenerate shape weights and exits)."""
+    cfg = _fp64(workloads.config(2, nx=16, ny=16, nz=8, shape=shape))
+    st = oracle.init_state(cfg)
+    oracle.step(st, 6)
+    r = workloads.rng(62)
+    for sp in st.species:
+        for c, n in (("x", 16), ("y", 16), ("z", 8)):
+            k = np.arange(n, dtype=np.float64)
+            cand = np.concatenate([k, k + 0.5, np.nextafter(k + 1, 0.0), np.nextafter(k, float(n))])
+            v = getattr(sp, c).copy()
+            pick = r.random(v.size) < 0.5
+            v[pick] = cand[r.integers(0, cand.size, int(pick.sum()))]
+            setattr(sp, c, v)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print("fp64 faces", shape, err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-12 and max(err["x"]) <= 1e-12 and err["J"] <= 1e-12
+
+
 def test_fp64_energy_trace_100_steps(P):
     cfg = _fp64(workloads.config(0))
     nsteps = cfg["steps"]

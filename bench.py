@@ -209,7 +209,7 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
                                     for m in ("exact", "mlp", "table")}
     out["table_rate_stage_speedup"] = out["exact"]["rate_ms"] / out["table"]["rate_ms"]
     out["table_whole_step_speedup"] = out["exact"]["total_ms"] / out["table"]["total_ms"]
-    # error of the surrogate against the exact quadrature (the judge)
+    # error of the surrogate against the exact quadrature (its reference)
     T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)
     ex = pic.rate_eval("exact", 1, T, ne, Z)
     ml = pic.rate_eval("mlp", 1, T, ne, Z)
@@ -271,8 +271,8 @@ def main(argv=None):
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is not implemented "
-                                   "(see DESIGN.md for how the path would shard)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding across GPUs is not implemented",
+                          "n_gpus": args.gpus}))
         return 2
 
     import torch

@@ -236,7 +236,7 @@ def test_mlp_training_converges(trained):
 
 def test_mlp_rate_error_and_gain_on_heldout_set(trained):
     """Median relative rate error <= 1 % against the exact GL-64 rate (the
-    judge), on held-out log-uniform inputs; the analytic prior alone is
+    reference), on held-out log-uniform inputs; the analytic prior alone is
     reported for the gain."""
     pic, _ = trained
     T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)

@@ -303,7 +303,7 @@ typedef struct {
 /* One ionisation step for every ionising species.  PIC_ERR_STATE if the
  * handle has no ionising species, or for PIC_RATE_MLP before a surrogate was
  * trained or loaded; PIC_ERR_CAPACITY if a supercell's electron frames are full
- * (ions whose electron does not fit are left unchanged). */
+ * (an ion keeps only the events whose electrons found a slot). */
 int pic_ionize(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* out);
 
 /* Per-cell n_e (cm^-3) and kT_e (eV) of the electrons that species `species`
@@ -312,8 +312,10 @@ int pic_ionize(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* out);
 int pic_cell_moments(pic_ctx* ctx, int species, double* ne_cm3, double* kT_ev);
 
 /* ln nu (nu in 1/s) for n host samples (kT_e eV, n_e cm^-3, charge state Z of
- * species `species`), by the exact quadrature or the surrogate (with its
- * exact fallback outside the trained range).  Synchronous. */
+ * species `species`), by the exact quadrature, the surrogate (with its exact
+ * fallback outside the trained range) or the table (built at first use; exact
+ * outside its kT range).  Synchronous.  -inf for Z outside [0, z_max) or a
+ * non-positive kT_e or n_e. */
 int pic_rate_eval(pic_ctx* ctx, pic_rate_mode_t mode, int species, int64_t n, const double* kT_ev,
                   const double* ne_cm3, const int32_t* Z, double* ln_rate);
 

@@ -177,40 +177,63 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     bool full = false;
     int fired = 0, active = 0;
-    for (int t = tid; t < n; t += BLOCK) {
-        const int64_t p = base + t;
-        const int Z0 = ion.zs[p];
-        if (Z0 >= tab.z_max) continue;
-        ++active;
-        // the ion's cell, for later events' rates and the energy account only
-        const bool need_cell = CHAIN || a.energy_loss;
-        const int64_t gi = need_cell ? (int64_t)(scx * SX + (int)ion.x[p]) +
-                                           (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) +
-                                                            (int64_t)g.ny * (scz * SZ + (int)ion.z[p]))
-                                     : 0;
-        const uint32_t id = ion.id[p];
-        const int nev = ion_events<CHAIN>(tab, a, id, Z0, nu[p], CHAIN ? db.kT[gi] : 0.0, CHAIN ? db.ne[gi] : 0.0,
-                                          glx, glw);
-        if (nev == 0) continue;
-        const int b = atomicAdd(&s_add, nev);
-        int done = 0;
-        double dE = 0.0;
-        for (int e = 0; e < nev; ++e) {
-            const int k = b + e;
-            if (k >= room) { full = true; break; }
-            const int64_t q = ebase64 + ebase + k;
-            const int znew = Z0 + e + 1;
-            el.x[q] = ion.x[p]; el.y[q] = ion.y[p]; el.z[q] = ion.z[p];
-            el.ux[q] = ion.ux[p]; el.uy[q] = ion.uy[p]; el.uz[q] = ion.uz[p];
-            el.w[q] = ion.w[p];
-            el.id[q] = (uint32_t)(a.id_base_new + (int64_t)(id - (uint32_t)a.ion_id_offset) * tab.z_max + (znew - 1));
-            dE += tab.P[Z0 + e];
-            ++done;
+    // chunks of DRAW_PER slots per lane: every load of a chunk is issued
+    // before the first decision, so the lanes wait on memory once per chunk
+    constexpr int DRAW_PER = 4;
+    for (int c0 = 0; c0 < n; c0 += BLOCK * DRAW_PER) {
+        int zs[DRAW_PER];
+        uint32_t ids[DRAW_PER];
+        double nus[DRAW_PER];
+#pragma unroll
+        for (int k = 0; k < DRAW_PER; ++k) {
+            const int t = c0 + k * BLOCK + tid;
+            zs[k] = tab.z_max;  // inactive
+            ids[k] = 0;
+            nus[k] = 0.0;
+            if (t < n) {
+                const int64_t p = base + t;
+                zs[k] = ion.zs[p];
+                ids[k] = ion.id[p];
+                nus[k] = nu[p];
+            }
         }
-        if (done) {
-            ion.zs[p] = (uint8_t)(Z0 + done);
-            fired += done;
-            if (a.energy_loss) atomicAdd(&db.de[gi], (double)ion.w[p] * dE);
+#pragma unroll
+        for (int k = 0; k < DRAW_PER; ++k) {
+            const int Z0 = zs[k];
+            if (Z0 >= tab.z_max) continue;
+            ++active;
+            const int64_t p = base + c0 + k * BLOCK + tid;
+            // the ion's cell, for later events' rates and the energy account only
+            const bool need_cell = CHAIN || a.energy_loss;
+            const int64_t gi = need_cell ? (int64_t)(scx * SX + (int)ion.x[p]) +
+                                               (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) +
+                                                                (int64_t)g.ny * (scz * SZ + (int)ion.z[p]))
+                                         : 0;
+            const uint32_t id = ids[k];
+            const int nev = ion_events<CHAIN>(tab, a, id, Z0, nus[k], CHAIN ? db.kT[gi] : 0.0,
+                                              CHAIN ? db.ne[gi] : 0.0, glx, glw);
+            if (nev == 0) continue;
+            const int b = atomicAdd(&s_add, nev);
+            int done = 0;
+            double dE = 0.0;
+            for (int e = 0; e < nev; ++e) {
+                const int kk = b + e;
+                if (kk >= room) { full = true; break; }
+                const int64_t q = ebase64 + ebase + kk;
+                const int znew = Z0 + e + 1;
+                el.x[q] = ion.x[p]; el.y[q] = ion.y[p]; el.z[q] = ion.z[p];
+                el.ux[q] = ion.ux[p]; el.uy[q] = ion.uy[p]; el.uz[q] = ion.uz[p];
+                el.w[q] = ion.w[p];
+                el.id[q] = (uint32_t)(a.id_base_new + (int64_t)(id - (uint32_t)a.ion_id_offset) * tab.z_max +
+                                      (znew - 1));
+                dE += tab.P[Z0 + e];
+                ++done;
+            }
+            if (done) {
+                ion.zs[p] = (uint8_t)(Z0 + done);
+                fired += done;
+                if (a.energy_loss) atomicAdd(&db.de[gi], (double)ion.w[p] * dE);
+            }
         }
     }
     if (full) g.flags[FLAG_CAPACITY] = 1;

@@ -92,12 +92,20 @@ __device__ inline int kperm(int s, int g, int j) { return 32 * s + 16 * (j >> 2)
 // Every part is multiplied exactly by its BF16 weight, so layer 1 is the
 // product of BF16 weights with the FP32 inputs plus the FP32 bias, up to the
 // order of the FP32 sums.
+// Inference runs the hidden layers in base 2: layer l computes z' = L z
+// (L = log2 e) and the activation s(z') = z' / (1 + 2^{-z'}) = L silu(z), so
+// that the activation needs no multiply before its exp2.  This folds L into
+// W1, b1 and b2 and 1/L into W3 (W2 is unchanged: L silu(z1) feeds z2' =
+// W2 (L silu(z1)) + L b2 = L z2).  The BF16 weights are rounded after the
+// scaling.
+constexpr float LOG2E = 1.44269504088896341f;
+
 __device__ inline float w1_aug(const float* P, int h, int k)
 {
-    if (k < 4) return bf16r(P[OFF_W1 + h * NIN + (k & 1)]);
-    if (k < 10) return bf16r(P[OFF_W1 + h * NIN + 2 + (k - 4)]);
+    if (k < 4) return bf16r(LOG2E * P[OFF_W1 + h * NIN + (k & 1)]);
+    if (k < 10) return bf16r(LOG2E * P[OFF_W1 + h * NIN + 2 + (k - 4)]);
     if (k > 12) return 0.0f;
-    const float b = P[OFF_B1 + h];
+    const float b = LOG2E * P[OFF_B1 + h];
     const float hi = bf16r(b), mid = bf16r(b - hi), lo = bf16r(b - hi - mid);
     return k == 10 ? hi : (k == 11 ? mid : lo);
 }
@@ -127,25 +135,29 @@ __device__ inline void load_net(const float* P, int lane, Net& n)
 #pragma unroll
             for (int j = 0; j < 8; ++j) n.a2[t][s][j] = (__bf16)P[OFF_W2 + (16 * t + c) * NH + kperm(s, g, j)];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) n.b2[t][e] = P[OFF_B2 + 16 * t + 4 * g + e];
+        for (int e = 0; e < 4; ++e) n.b2[t][e] = LOG2E * P[OFF_B2 + 16 * t + 4 * g + e];
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) n.a3[s][j] = (__bf16)((c & 3) == 0 ? P[OFF_W3 + kperm(s, g, j)] : 0.0f);
+        for (int j = 0; j < 8; ++j)
+            n.a3[s][j] = (__bf16)((c & 3) == 0 ? P[OFF_W3 + kperm(s, g, j)] * (1.0f / LOG2E) : 0.0f);
     n.b3 = P[OFF_B3];
     n.zbase = g == 1 ? 0 : (g == 2 ? 4 : 64);                  // one-hot columns 0..3 and 4..5
     n.cbits = g == 2 ? 0x3F803F8000000000ull : (g == 3 ? 0x3F80ull : 0ull);  // b1 hi, mid | b1 lo
 }
 
-// SiLU of a result tile pair, packed as the next layer's B operand for K step s.
+// Base-2 SiLU s(z) = z / (1 + 2^{-z}) (hardware exp2 and reciprocal).
+__device__ inline float silu2(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z)); }
+
+// Base-2 SiLU of a result tile pair, packed as the next layer's B operand for K step s.
 __device__ inline bf16x8 silu_pack(const floatx4& lo, const floatx4& hi)
 {
     bf16x8 r;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        r[e] = (__bf16)silu(lo[e]);
-        r[4 + e] = (__bf16)silu(hi[e]);
+        r[e] = (__bf16)silu2(lo[e]);
+        r[4 + e] = (__bf16)silu2(hi[e]);
     }
     return r;
 }

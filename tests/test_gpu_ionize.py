@@ -183,12 +183,13 @@ def test_mlp_gradient_matches_oracle_backprop(P):
 
 def test_mlp_inference_matches_oracle_forward(P):
     """The fused inference kernel (transposed MFMA layout, augmented layer-1 K,
-    head on MFMA) evaluates the same network as the oracle's plain FP64
-    forward.  With BF16 weights on both sides, the GPU differs only by BF16
-    rounding of the 128 activations (relative 2^-9 each), FP32 sums and the
-    FP32 prior; per sample, |d ln nu| must stay within s times the
-    first-order bound of the activation rounding propagated through W2, SiLU'
-    and W3, plus 1e-4 for the FP32 parts."""
+    head on MFMA, hidden layers in base 2) evaluates the same network as the
+    oracle's plain FP64 forward.  The GPU differs by the BF16 rounding of the
+    128 activations (relative 2^-9 each), by the BF16 re-rounding of W1 and
+    W3 after the base-2 scaling (log2 e into W1, 1/log2 e into W3; relative
+    2^-9 each), FP32 sums and the FP32 prior; per sample, |d ln nu| must stay
+    within s times the first-order bound of those roundings propagated
+    through SiLU', W2 and W3, plus 1e-4 for the FP32 parts."""
     cfg = _carbon_cfg((8, 8, 4))
     r = workloads.rng(31)
     p = mlp.init_params(5)
@@ -206,9 +207,12 @@ def test_mlp_inference_matches_oracle_forward(P):
         pic.mlp_set_params(1, flat, [mu, s], [1.0, 1e4, 1e19, 1e23])
         got = pic.rate_eval("mlp", 1, T, ne, Z)
     want = mlp.ln_rate(pref, mu, s, T, ne, Z, Pt, qt)
-    _, c = mlp.forward(pref, mlp.features(T, ne, Z))
-    dz2 = (np.abs(c["h1"]) * 2.0**-9) @ np.abs(pref["W2"]).T
-    bound = (np.abs(mlp.dsilu(c["z2"])) * dz2 + np.abs(c["h2"]) * 2.0**-9) @ np.abs(pref["W3"][0])
+    X = mlp.features(T, ne, Z)
+    _, c = mlp.forward(pref, X)
+    dz1 = 2.0**-9 * (np.abs(X) @ np.abs(pref["W1"]).T)                       # W1 re-rounding
+    dh1 = np.abs(c["h1"]) * 2.0**-9 + np.abs(mlp.dsilu(c["z1"])) * dz1       # + activation rounding
+    dz2 = dh1 @ np.abs(pref["W2"]).T
+    bound = (np.abs(mlp.dsilu(c["z2"])) * dz2 + 2 * np.abs(c["h2"]) * 2.0**-9) @ np.abs(pref["W3"][0])  # + W3
     err = np.abs(got - want)
     _print("inference vs oracle: max", err.max(), "median", np.median(err), "max err/bound",
            (err / (s * bound + 1e-4)).max())

@@ -2,12 +2,12 @@
  * pic.h - C ABI of the MI355X (gfx950) particle-in-cell hot path.
  *
  * The library advances a relativistic 3D3V particle-in-cell plasma on one GPU:
- * field gather (CIC or TSC shape on Yee-staggered E, B), relativistic Boris
- * push, Esirkepov charge-conserving current deposition and the Yee FDTD field
- * update, on particles kept sorted into 8x8x4-cell supercells ("frames" of 256
- * slots per supercell), plus a Monte Carlo electron-impact ionisation step
- * whose rates come from an exact FP64 Gauss-Laguerre quadrature or from a
- * small learned surrogate.  The paper names these methods for its benchmark
+ * field gather (CIC, TSC or PCS shape on Yee-staggered E, B; standard or
+ * Galerkin), relativistic Boris push, Esirkepov charge-conserving current
+ * deposition and the Yee FDTD field update, on particles kept sorted into
+ * 8x8x4-cell supercells ("frames" of 256 slots per supercell), in FP32 or FP64,
+ * plus a Monte Carlo electron-impact ionisation step whose rates come from an
+ * exact FP64 Gauss-Laguerre quadrature, a small learned surrogate or a table.  The paper names these methods for its benchmark
  * (section "Evaluation": Boris pusher, Esirkepov current solver, Yee field
  * solver, separable field interpolation, 3D3V, TSC shape) and describes the
  * supercell / frame data structure and the block-per-supercell mapping

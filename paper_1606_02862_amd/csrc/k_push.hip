@@ -281,7 +281,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         if (slot >= n) break;
         const unsigned u = RB * (unsigned)slot;  // byte offset of the slot
         const R x0 = nx0, y0 = ny0, z0 = nz0;
-        R ux = nux, uy = nuy, uz = nuz;
+        const R ux0 = nux, uy0 = nuy, uz0 = nuz;
         const R wgt = nw;
         R q = s.charge;
         if constexpr (HAS_Z) q *= (R)nzs;
@@ -316,25 +316,38 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
 
         // ---- relativistic Boris: half kick, rotation, half kick
         const R h = q * qm;
-        const R umx = rfma(h, Ex, ux), umy = rfma(h, Ey, uy), umz = rfma(h, Ez, uz);
+        const R umx = rfma(h, Ex, ux0), umy = rfma(h, Ey, uy0), umz = rfma(h, Ez, uz0);
         const R hg = h * rrsq(R(1) + umx * umx + umy * umy + umz * umz);
         const R tx = hg * Bx, ty = hg * By, tz = hg * Bz;
         const R sf = R(2) * rrcp(R(1) + tx * tx + ty * ty + tz * tz);
         const R upx = umx + (umy * tz - umz * ty);
         const R upy = umy + (umz * tx - umx * tz);
         const R upz = umz + (umx * ty - umy * tx);
-        ux = rfma(h, Ex, umx + sf * (upy * tz - upz * ty));
-        uy = rfma(h, Ey, umy + sf * (upz * tx - upx * tz));
-        uz = rfma(h, Ez, umz + sf * (upx * ty - upy * tx));
+        R ux = rfma(h, Ex, umx + sf * (upy * tz - upz * ty));
+        R uy = rfma(h, Ey, umy + sf * (upz * tx - upx * tz));
+        R uz = rfma(h, Ez, umz + sf * (upx * ty - upy * tx));
 
         // ---- move
         const R ig = rrsq(R(1) + ux * ux + uy * uy + uz * uz);
         const R ddx = cdx * ux * ig, ddy = cdy * uy * ig, ddz = cdz * uz * ig;
-        if (!(rabs(ddx) < R(1) && rabs(ddy) < R(1) && rabs(ddz) < R(1))) {
-            bad = true;  // a displacement of a cell or more (or NaN): keep the particle where it was
-            continue;
+        // a displacement of a cell or more (or NaN) keeps the particle where it
+        // was, momentum included, and is reported.  In FP32 no branch leaves
+        // the iteration here, so every lane reaches the stores below: a path
+        // without them makes the compiler wait for all of this frame's stores
+        // before the next frame's prefetched values can be used.  The FP64
+        // instantiations keep the early exit (with the branch-free form the
+        // FP64 PCS kernel, which spills, deposited wrong currents although its
+        // IR differs only by the selects).
+        const bool ok = rabs(ddx) < R(1) && rabs(ddy) < R(1) && rabs(ddz) < R(1);
+        if constexpr (std::is_same<R, double>::value) {
+            if (!ok) {
+                bad = true;
+                continue;
+            }
         }
-        const R x1 = x0 + ddx, y1 = y0 + ddy, z1 = z0 + ddz;
+        bad |= !ok;
+        if (!ok) { ux = ux0; uy = uy0; uz = uz0; }
+        const R x1 = ok ? x0 + ddx : x0, y1 = ok ? y0 + ddy : y0, z1 = ok ? z0 + ddz : z0;
 
         // ---- current: in line when the first shape node is unchanged on every axis
         const R qw = q * wgt;

@@ -217,6 +217,12 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     R(*fB)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem + 3 * T::GN * RB);
     A* tJ = reinterpret_cast<A*>(smem + 6 * T::GN * RB);
     __shared__ int s_holes, s_queue, s_cnt[3];
+    // FP32 CIC: each wave appends its queued particles to a region of its own
+    // (no LDS atomic, and no wait on one, inside the frame loop); measured 1 %
+    // faster for CIC and 2-3 % slower for TSC, which keeps the shared queue
+    constexpr bool WAVEQ = std::is_same<R, float>::value && ORDER == 1;
+    constexpr int NW = NT / 64;
+    __shared__ int s_qn[NW];
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
     // arrivals of the previous step first (frames dense again before pushing)
@@ -244,6 +250,9 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     for (int t = tid; t < 3 * T::JN; t += NT) tJ[t] = A(0);
     if (tid == 0) { s_holes = 0; s_queue = 0; }
     __syncthreads();
+    const int wave = tid >> 6;
+    const int rw = g.qcap / NW;  // queue region of one wave: >= its slots of every frame
+    int qn = 0;                  // records this wave has queued (the same in all its active lanes)
 
     const int n = s.count[sc];
     const int64_t base = (int64_t)sc * s.cap;
@@ -371,10 +380,16 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         // one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 -
         const unsigned long long qmask = __ballot(!same);
         if (qmask) {
-            const int leader = __ffsll((long long)qmask) - 1;
-            int qb = 0;
-            if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
-            qb = __shfl(qb, leader, 64);
+            int qb;
+            if constexpr (WAVEQ) {
+                qb = wave * rw + qn;
+                qn += __popcll(qmask);
+            } else {
+                const int leader = __ffsll((long long)qmask) - 1;
+                qb = 0;
+                if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
+                qb = __shfl(qb, leader, 64);
+            }
             if (!same) {
                 R4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
                 e[0] = make4(x0, y0, z0, qw);
@@ -394,7 +409,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
             const int leader = __ffsll((long long)lmask) - 1;
             int hb = 0;
             if (lane == leader) hb = atomicAdd(&s_holes, __popcll(lmask));
-            hb = __shfl(hb, leader, 64);
+            if constexpr (WAVEQ) hb = __builtin_amdgcn_readlane(hb, leader);
+            else hb = __shfl(hb, leader, 64);
             const int hidx = hb + __popcll(lmask & ((1ull << lane) - 1ull));
             if (left) {
                 if (hidx < s.cap_in) {
@@ -410,12 +426,27 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         }
     }
     if (bad) g.flags[FLAG_CFL] = 1;
+    // lane 0 of a wave takes part in every frame its wave does, so it holds the count
+    if (WAVEQ && lane == 0) s_qn[wave] = qn;
     __syncthreads();
 
     // ---- queued particles: general (ORDER+2)-node window, all lanes busy
-    const int nq = s_queue;
+    int qpre[NW];  // per-wave queues: first queue index of each wave's records
+    int nq = 0;
+    if constexpr (WAVEQ) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { qpre[w] = nq; nq += s_qn[w]; }
+    } else {
+        nq = s_queue;
+    }
     for (int t = tid; t < nq; t += NT) {
-        const R4* e = g.qbuf + 2 * (qbase + t);
+        int rec = t;
+        if constexpr (WAVEQ) {  // the last wave whose first index is <= t (waves may queue none)
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                if (t >= qpre[k]) rec = k * rw + (t - qpre[k]);
+        }
+        const R4* e = g.qbuf + 2 * (qbase + rec);
         const R4 a = e[0], b = e[1];
         const R x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
         const R x1 = b.x, y1 = b.y, z1 = b.z;
@@ -502,7 +533,9 @@ template <class R>
 hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, bool galerkin, double vmax,
                        int apar, int wpar, hipStream_t st)
 {
-    if (s.cap > g.qcap) return hipErrorInvalidValue;  // the deposit queue must hold a full supercell
+    // the deposit queue holds a full supercell, split evenly over the waves of a workgroup
+    const int nt = order == 1 ? 256 : 512;
+    if ((s.cap + nt - 1) / nt * nt > g.qcap || g.qcap % (nt / 64) != 0) return hipErrorInvalidValue;
     if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
     R jscale = R(1), jinv = R(1);
     if constexpr (std::is_same<R, float>::value) {

@@ -762,6 +762,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     // one deposit queue shared by the species (their particle kernels run one after another)
     g.qcap = 0;
     for (int s = 0; s < n_species; ++s) g.qcap = std::max(g.qcap, c->sp[s].v.cap);
+    g.qcap = (g.qcap + 511) / 512 * 512;  // whole 512-lane workgroups' worth of slots
     g64.qcap = g.qcap;
     const bool q_ok = c->fp64 ? (g64.qbuf = (double4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(double4))) != nullptr
                               : (g.qbuf = (float4*)dev_alloc(c, (size_t)2 * g.nsc * g.qcap * sizeof(float4))) != nullptr;

@@ -42,7 +42,7 @@ struct GridViewT {
     R* J;
     int32_t* flags;
     typename Vec4<R>::type* qbuf;  // deposit queue: nsc * qcap records of 2 (x0,y0,z0,qw | x1,y1,z1,-)
-    int qcap;              // queue slots per supercell (>= every species' frame capacity)
+    int qcap;              // queue slots per supercell (>= every species' frame capacity; a multiple of 512)
 };
 
 template <class R>

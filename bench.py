@@ -170,9 +170,9 @@ def counter_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_wr
 def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     """Monte Carlo ionisation on the 128^3 electron-carbon workload: GPU time
     of the rate stage and of the whole step with the exact FP64 GL-64
-    quadrature, with the BF16-MFMA surrogate (trained first on the GPU) and
-    with the tabulated rate, and their rate errors against the exact
-    quadrature."""
+    quadrature, with the BF16-MFMA surrogate (trained first on the GPU; SiLU
+    as configured, and the same network with ReLU as a second line) and with
+    the tabulated rate, and their rate errors against the exact quadrature."""
     import numpy as np
     cfg = workloads.config(3)
     gc = cfg["grid"]
@@ -180,9 +180,13 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     pic = P.Pic(cfg)
     rep = pic.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **workloads.MLP_TRAIN)
     trained = pic.mlp_get_params(1)
+    # the same network and recipe with ReLU hidden activations, on a second handle
+    pic_relu = P.Pic(cfg)
+    rep_relu = pic_relu.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **dict(workloads.MLP_TRAIN, activation="relu"))
+    trained_relu = pic_relu.mlp_get_params(1)
     pic.step(2)
     out = {"workload": workloads.config(4)["workload"], "ions": ncell * cfg["species"][1]["ppc"],
-           "electrons_initial": ncell * cfg["species"][0]["ppc"], "train": rep}
+           "electrons_initial": ncell * cfg["species"][0]["ppc"], "train": rep, "train_relu": rep_relu}
 
     def one_call(mode):
         # a fresh handle per call: every mode and repeat ionises the same state
@@ -190,14 +194,16 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
         h = P.Pic(cfg)
         if mode == "mlp":
             h.mlp_set_params(1, *trained)
+        if mode == "mlp_relu":
+            h.mlp_set_params(1, *trained_relu)
         if mode == "table":
             h.rate_eval("table", 1, [100.0], [1e21], [2])   # builds the table (once per handle)
         h.step(2)
-        r = h.ionize(mode)
+        r = h.ionize("mlp" if mode == "mlp_relu" else mode)
         h.close()
         return r
 
-    for mode in ("exact", "mlp", "table"):
+    for mode in ("exact", "mlp", "table", "mlp_relu"):
         runs = [one_call(mode) for _ in range(repeats)]
         out[mode] = {"rate_ms": min(r["rate_ms"] for r in runs), "total_ms": min(r["total_ms"] for r in runs),
                      "ionized_per_call": [r["ionized"] for r in runs], "fallback": runs[-1]["fallback"],
@@ -206,9 +212,11 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     # the whole pic_ionize (cell moments + rate + draw/append; moments and draw are the same in both modes)
     out["whole_step_speedup"] = out["exact"]["total_ms"] / out["mlp"]["total_ms"]
     out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3)
-                                    for m in ("exact", "mlp", "table")}
+                                    for m in ("exact", "mlp", "table", "mlp_relu")}
     out["table_rate_stage_speedup"] = out["exact"]["rate_ms"] / out["table"]["rate_ms"]
     out["table_whole_step_speedup"] = out["exact"]["total_ms"] / out["table"]["total_ms"]
+    out["mlp_relu_rate_stage_speedup"] = out["exact"]["rate_ms"] / out["mlp_relu"]["rate_ms"]
+    out["mlp_relu_whole_step_speedup"] = out["exact"]["total_ms"] / out["mlp_relu"]["total_ms"]
     # error of the surrogate against the exact quadrature (its reference)
     T, ne, Z = workloads.loguniform_rate_inputs(workloads.MLP_HELDOUT_SEED, 1_000_000)
     ex = pic.rate_eval("exact", 1, T, ne, Z)
@@ -226,6 +234,7 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     out["mlp_error_heldout"] = stats(rel)
     out["table_error_heldout"] = stats(np.abs(np.expm1(pic.rate_eval("table", 1, T, ne, Z) - ex)))
     out["prior_only_error_heldout"] = stats(relp)
+    out["mlp_relu_error_heldout"] = stats(np.abs(np.expm1(pic_relu.rate_eval("mlp", 1, T, ne, Z) - ex)))
     # live population: every cell's (n_e, kT_e) with the charge states present
     ne_c, kT_c = pic.cell_moments(1)
     ok = (ne_c > 0) & (kT_c > 0)
@@ -234,6 +243,7 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     rl = np.abs(np.expm1(pic.rate_eval("mlp", 1, lt, ln, zz) - pic.rate_eval("exact", 1, lt, ln, zz)))
     out["mlp_error_live_cells_Z2"] = stats(rl)
     pic.close()
+    pic_relu.close()
     if cpu:
         import oracle.ionize as oi
         Ts, ns, Zs = T[:200_000], ne[:200_000], Z[:200_000]

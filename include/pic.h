@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 4
+#define PIC_ABI_VERSION 5
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
 #define PIC_LOTZ_SHELLS 3
@@ -325,7 +325,8 @@ int pic_rate_eval(pic_ctx* ctx, pic_rate_mode_t mode, int species, int64_t n, co
 int pic_gauss_laguerre64(double* nodes, double* weights);
 
 /* ------------------------------------------------------------------------
- * Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1, SiLU activations.
+ * Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1, SiLU (default) or
+ * ReLU activations on both hidden layers.
  *   inputs  (log10 kT_e - 2)/2, (log10 n_e - 21)/2, one-hot of Z (6 states);
  *   output  ln nu = ln nu_prior + mu + s * y, where ln nu_prior is the rate
  *           with e^z E1(z) (z = P/kT) replaced by ln(1 + 1/z):
@@ -338,6 +339,11 @@ int pic_gauss_laguerre64(double* nodes, double* weights);
  * ------------------------------------------------------------------------ */
 #define PIC_MLP_NPARAM 4801
 
+/* Hidden-layer activations.  SiLU needs an exp2 and a reciprocal per hidden
+ * unit (128 transcendental pairs per ion), ReLU one max. */
+#define PIC_MLP_SILU 0   /* z sigmoid(z) */
+#define PIC_MLP_RELU 1   /* max(z, 0); derivative 1 for z > 0, else 0 */
+
 typedef struct {
     int64_t n_train;       /* training samples (exact labels generated on the GPU) */
     int32_t batch;         /* minibatch size (multiple of 64) */
@@ -346,6 +352,8 @@ typedef struct {
     double lr_final;
     uint64_t seed;         /* Philox key of sample generation, batch draws and init */
     double t_min_ev, t_max_ev, n_min_cm3, n_max_cm3;  /* log-uniform sampling ranges */
+    int32_t activation;    /* PIC_MLP_SILU or PIC_MLP_RELU; the trained network keeps it */
+    int32_t reserved;      /* 0 */
 } pic_mlp_train_cfg_t;
 
 typedef struct {
@@ -361,12 +369,16 @@ typedef struct {
  * FP32 accumulation) and Adam (FP32 master weights) kernels. */
 int pic_mlp_train(pic_ctx* ctx, int species, const pic_mlp_train_cfg_t* cfg, pic_mlp_report_t* out);
 
-/* Copy the FP32 master parameters (PIC_MLP_NPARAM floats) and (mu, s) out /
- * in.  set also defines the trained range (t/n min/max, 4 doubles). */
-int pic_mlp_get_params(pic_ctx* ctx, int species, float* params, double* mu_s, double* range);
-int pic_mlp_set_params(pic_ctx* ctx, int species, const float* params, const double* mu_s, const double* range);
+/* Copy the FP32 master parameters (PIC_MLP_NPARAM floats), (mu, s), the
+ * trained range (t/n min/max, 4 doubles) and the activation out / in.  get
+ * skips NULL outputs; set needs params and mu_s, keeps the range when range
+ * is NULL, and rejects an activation other than PIC_MLP_SILU / PIC_MLP_RELU. */
+int pic_mlp_get_params(pic_ctx* ctx, int species, float* params, double* mu_s, double* range, int32_t* activation);
+int pic_mlp_set_params(pic_ctx* ctx, int species, const float* params, const double* mu_s, const double* range,
+                       int32_t activation);
 
-/* One forward + backward pass of the training kernels on n host samples
+/* One forward + backward pass of the training kernels (with the species'
+ * current activation) on n host samples
  * (features X[n][8], targets t[n]) with the current parameters: writes the
  * mean squared error and its gradient (PIC_MLP_NPARAM floats).  n must be a
  * multiple of 64.  Synchronous. */

@@ -4,8 +4,9 @@
 The network replaces the per-ion Maxwellian-averaged Lotz quadrature:
   inputs  x0 = (log10 T_e[eV] - 2)/2, x1 = (log10 n_e[cm^-3] - 21)/2,
           x2..x7 = one-hot of the charge state Z in 0..5;
-  layers  h1 = SiLU(W1 x + b1), h2 = SiLU(W2 h1 + b2), y = W3 h2 + b3,
-          SiLU(z) = z sigmoid(z), widths 8 -> 64 -> 64 -> 1;
+  layers  h1 = f(W1 x + b1), h2 = f(W2 h1 + b2), y = W3 h2 + b3, widths
+          8 -> 64 -> 64 -> 1, with f = SiLU(z) = z sigmoid(z) (the default) or
+          f = ReLU(z) = max(z, 0) (derivative taken as 1 for z > 0, else 0);
   output  ln nu = ln nu_prior + mu + s * y, where the prior is the rate with
           e^z E1(z) replaced by its upper bound ln(1 + 1/z), z = P/kT:
           ln nu_prior = ln(n_e vbar a q / (P kT)) - z + ln ln(1 + 1/z).
@@ -51,6 +52,17 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
+def relu(z):
+    return np.maximum(z, 0.0)
+
+
+def drelu(z):
+    return (np.asarray(z) > 0.0).astype(np.float64)
+
+
+ACTIVATIONS = {"silu": (silu, dsilu), "relu": (relu, drelu)}
+
+
 def init_params(seed: int):
     """He-style uniform initial weights (any fixed initialisation will do)."""
     r = np.random.default_rng(seed)
@@ -60,18 +72,20 @@ def init_params(seed: int):
     return dict(W1=W1, b1=np.zeros(N_H), W2=W2, b2=np.zeros(N_H), W3=W3, b3=np.zeros(1))
 
 
-def forward(p, X):
+def forward(p, X, act: str = "silu"):
+    f = ACTIVATIONS[act][0]
     z1 = X @ p["W1"].T + p["b1"]
-    h1 = silu(z1)
+    h1 = f(z1)
     z2 = h1 @ p["W2"].T + p["b2"]
-    h2 = silu(z2)
+    h2 = f(z2)
     y = h2 @ p["W3"].T + p["b3"]
     return y[:, 0], dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
-def loss_and_grad(p, X, t):
+def loss_and_grad(p, X, t, act: str = "silu"):
     """MSE loss mean((y - t)^2) and its analytic gradient (backpropagation)."""
-    y, c = forward(p, X)
+    df = ACTIVATIONS[act][1]
+    y, c = forward(p, X, act)
     B = X.shape[0]
     r = y - t
     loss = float(np.mean(r * r))
@@ -80,26 +94,26 @@ def loss_and_grad(p, X, t):
     g["W3"] = dy.T @ c["h2"]
     g["b3"] = dy.sum(axis=0)
     dh2 = dy @ p["W3"]
-    dz2 = dh2 * dsilu(c["z2"])
+    dz2 = dh2 * df(c["z2"])
     g["W2"] = dz2.T @ c["h1"]
     g["b2"] = dz2.sum(axis=0)
     dh1 = dz2 @ p["W2"]
-    dz1 = dh1 * dsilu(c["z1"])
+    dz1 = dh1 * df(c["z1"])
     g["W1"] = dz1.T @ c["X"]
     g["b1"] = dz1.sum(axis=0)
     return loss, g
 
 
-def ln_rate(p, mu, s, T_eV, ne_cm3, Z, P_table, q_table, a_table=None):
+def ln_rate(p, mu, s, T_eV, ne_cm3, Z, P_table, q_table, a_table=None, act: str = "silu"):
     """Surrogate ln nu for given inputs (FP64 evaluation of the network);
     P, q, a of each state's outermost subshell (a defaults to 4.5e-14)."""
     Z = np.asarray(Z).astype(np.int64)
     P = np.asarray(P_table, dtype=np.float64)[Z]
     q = np.asarray(q_table, dtype=np.float64)[Z]
     a = LOTZ_A if a_table is None else np.asarray(a_table, dtype=np.float64)[Z]
-    y, _ = forward(p, features(T_eV, ne_cm3, Z))
+    y, _ = forward(p, features(T_eV, ne_cm3, Z), act)
     return ln_rate_prior(T_eV, ne_cm3, P, q, a) + mu + s * y
 
 
-__all__ = ["features", "ln_rate_prior", "silu", "forward", "loss_and_grad", "init_params", "ln_rate",
-           "ME_C2_EV"]
+__all__ = ["features", "ln_rate_prior", "silu", "relu", "ACTIVATIONS", "forward", "loss_and_grad", "init_params",
+           "ln_rate", "ME_C2_EV"]

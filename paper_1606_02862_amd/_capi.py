@@ -81,7 +81,8 @@ class IonizeStatsT(C.Structure):
 class MlpTrainCfgT(C.Structure):
     _fields_ = [("n_train", C.c_int64), ("batch", C.c_int32), ("steps", C.c_int32), ("lr", C.c_double),
                 ("lr_final", C.c_double), ("seed", C.c_uint64), ("t_min_ev", C.c_double), ("t_max_ev", C.c_double),
-                ("n_min_cm3", C.c_double), ("n_max_cm3", C.c_double)]
+                ("n_min_cm3", C.c_double), ("n_max_cm3", C.c_double), ("activation", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class MlpReportT(C.Structure):
@@ -90,6 +91,7 @@ class MlpReportT(C.Structure):
 
 
 PIC_MLP_NPARAM = 4801
+PIC_MLP_SILU, PIC_MLP_RELU = 0, 1
 PIC_RATE_EXACT, PIC_RATE_MLP = 0, 1
 
 _DP = C.POINTER(C.c_double)
@@ -119,8 +121,8 @@ SIGNATURES = {
     "pic_rate_eval": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),
     "pic_gauss_laguerre64": (C.c_int, [_DP, _DP]),
     "pic_mlp_train": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(MlpTrainCfgT), C.POINTER(MlpReportT)]),
-    "pic_mlp_get_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP]),
-    "pic_mlp_set_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP]),
+    "pic_mlp_get_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP, C.POINTER(C.c_int32)]),
+    "pic_mlp_set_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP, C.c_int32]),
     "pic_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _FP, _FP, _DP, _FP]),
     "pic_destroy": (C.c_int, [C.c_void_p]),
     "pic_last_error": (C.c_char_p, [C.c_void_p]),

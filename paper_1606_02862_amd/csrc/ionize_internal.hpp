@@ -84,6 +84,7 @@ struct MlpLaunch {
     const float* params;   // FP32 master parameters (PIC_MLP_NPARAM)
     double mu, s;          // target standardisation
     double t_min, t_max, n_min, n_max;
+    int act;               // PIC_MLP_SILU or PIC_MLP_RELU
 };
 struct MlpGen {
     double lt_min, lt_max, ln_min, ln_max;  // log10 ranges of kT (eV) and n_e (cm^-3)
@@ -95,6 +96,7 @@ struct MlpStep {
     int batch;             // multiple of 64
     uint64_t draw_seed;    // 0: samples 0..batch-1 in order; else Philox draws
     int64_t step;
+    int act;               // PIC_MLP_SILU or PIC_MLP_RELU
 };
 // fb_list: one entry per ion slot (nsc * cap), for the out-of-range ions
 hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonTables& tab, const MlpLaunch& ml,

@@ -1,12 +1,13 @@
-// Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1 network with SiLU,
-// BF16 weights and activations on the matrix cores, FP32 accumulation.
+// Learned ionisation-rate surrogate: 8 -> 64 -> 64 -> 1 network with SiLU or
+// ReLU hidden activations (a template parameter of every kernel), BF16
+// weights and activations on the matrix cores, FP32 accumulation.
 //
 // Wave tiling: a wave evaluates 16 samples at a time.  Lane l works on sample
 // l % 16 for layer 1 and on hidden units 8*(l/16) + j (+32) so that its
 // activations are directly the A operand of v_mfma_f32_16x16x32_bf16
 // (A[i][k]: lane i + 16*(k/8) holds k % 8); layer 2 is 2 K-steps x 4 N-tiles
 // = 8 MFMAs with W2 held in registers as the B operand; the result tile
-// (D[i][n]: lane n%16 + 16*(i/4) holds i % 4) gets b2 + SiLU and the dot
+// (D[i][n]: lane n%16 + 16*(i/4) holds i % 4) gets b2 + the activation and the dot
 // with W3 as per-lane partial sums reduced over the 16 lanes of a row group.
 // Layer 1 (2 continuous inputs + one-hot charge state) is a VALU column
 // gather; the prior and the exact fallback are an FP32 / FP64 epilogue.
@@ -36,6 +37,17 @@ __device__ inline float dsilu(float z)
 {
     const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
+}
+// The hidden activation and its derivative (ReLU': 1 for z > 0, else 0).
+template <int ACT> __device__ inline float act_f(float z)
+{
+    if constexpr (ACT == PIC_MLP_RELU) return fmaxf(z, 0.0f);
+    else return silu(z);
+}
+template <int ACT> __device__ inline float dact_f(float z)
+{
+    if constexpr (ACT == PIC_MLP_RELU) return z > 0.0f ? 1.0f : 0.0f;
+    else return dsilu(z);
 }
 
 // Per charge state z: P_z, and the constant of the analytic prior (the
@@ -97,7 +109,8 @@ __device__ inline int kperm(int s, int g, int j) { return 32 * s + 16 * (j >> 2)
 // that the activation needs no multiply before its exp2.  This folds L into
 // W1, b1 and b2 and 1/L into W3 (W2 is unchanged: L silu(z1) feeds z2' =
 // W2 (L silu(z1)) + L b2 = L z2).  The BF16 weights are rounded after the
-// scaling.
+// scaling.  ReLU commutes with the positive factor (max(L z, 0) = L max(z, 0)),
+// so the same scaled weights serve both activations.
 constexpr float LOG2E = 1.44269504088896341f;
 
 __device__ inline float w1_aug(const float* P, int h, int k)
@@ -150,14 +163,20 @@ __device__ inline void load_net(const float* P, int lane, Net& n)
 // Base-2 SiLU s(z) = z / (1 + 2^{-z}) (hardware exp2 and reciprocal).
 __device__ inline float silu2(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z)); }
 
-// Base-2 SiLU of a result tile pair, packed as the next layer's B operand for K step s.
-__device__ inline bf16x8 silu_pack(const floatx4& lo, const floatx4& hi)
+// The activation (base-2 SiLU, or ReLU) of a result tile pair, packed as the
+// next layer's B operand for K step s.
+template <int ACT> __device__ inline float act2(float z)
+{
+    if constexpr (ACT == PIC_MLP_RELU) return fmaxf(z, 0.0f);
+    else return silu2(z);
+}
+template <int ACT> __device__ inline bf16x8 act_pack(const floatx4& lo, const floatx4& hi)
 {
     bf16x8 r;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        r[e] = (__bf16)silu2(lo[e]);
-        r[4 + e] = (__bf16)silu2(hi[e]);
+        r[e] = (__bf16)act2<ACT>(lo[e]);
+        r[4 + e] = (__bf16)act2<ACT>(hi[e]);
     }
     return r;
 }
@@ -166,7 +185,7 @@ __device__ inline bf16x8 silu_pack(const floatx4& lo, const floatx4& hi)
 // BF16 pairs (x0_hi, x1_hi) and (x0_mid, x1_mid), and the charge state z;
 // every group the same sample).  Returns y of sample c in every lane of
 // column c.
-__device__ inline float forward16(const Net& n, int g, uint32_t xhi, uint32_t xmid, int z)
+template <int ACT> __device__ inline float forward16(const Net& n, int g, uint32_t xhi, uint32_t xmid, int z)
 {
     const unsigned d = (unsigned)(z - n.zbase);
     const uint64_t onehot = d < 4u ? (0x3F80ull << (16u * d)) : 0ull;
@@ -177,14 +196,14 @@ __device__ inline float forward16(const Net& n, int g, uint32_t xhi, uint32_t xm
     floatx4 d1[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) d1[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(n.a1[t], xb, zero, 0, 0, 0);
-    const bf16x8 h1a = silu_pack(d1[0], d1[1]), h1b = silu_pack(d1[2], d1[3]);
+    const bf16x8 h1a = act_pack<ACT>(d1[0], d1[1]), h1b = act_pack<ACT>(d1[2], d1[3]);
     floatx4 d2[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         d2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[t][0], h1a, n.b2[t], 0, 0, 0);
         d2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a2[t][1], h1b, d2[t], 0, 0, 0);
     }
-    const bf16x8 h2a = silu_pack(d2[0], d2[1]), h2b = silu_pack(d2[2], d2[3]);
+    const bf16x8 h2a = act_pack<ACT>(d2[0], d2[1]), h2b = act_pack<ACT>(d2[2], d2[3]);
     floatx4 d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[0], h2a, zero, 0, 0, 0);
     d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(n.a3[1], h2b, d3, 0, 0, 0);
     return d3[0] + n.b3;  // row 4g of the head tile: y of sample c
@@ -205,7 +224,7 @@ __device__ inline void split_inputs(float x0, float x1, uint32_t& hi, uint32_t& 
 // Forward of the 64 samples a wave holds, one per lane (z < 0: no sample).
 // Sub-tile q takes the samples of lanes 16q..16q+15; its result for sample
 // 16q + c lands in lane c + 16g for every g, so lane 16q + c reads its own.
-__device__ inline float forward64(const Net& n, int lane, float x0, float x1, int z)
+template <int ACT> __device__ inline float forward64(const Net& n, int lane, float x0, float x1, int z)
 {
     const int g = lane >> 4;
     uint32_t xhi, xmid;
@@ -217,7 +236,7 @@ __device__ inline float forward64(const Net& n, int lane, float x0, float x1, in
         const int zq = __shfl(z, src, 64);
         if (__ballot(zq >= 0) == 0) continue;  // wave-uniform: the 16 samples are the same in every group
         const uint32_t hq = (uint32_t)__shfl((int)xhi, src, 64), mq = (uint32_t)__shfl((int)xmid, src, 64);
-        const float yq = forward16(n, g, hq, mq, zq);
+        const float yq = forward16<ACT>(n, g, hq, mq, zq);
         if (g == q) y = yq;
     }
     return y;
@@ -247,6 +266,7 @@ struct MlpArgs {
 // kernel's occupancy.  Persistent workgroups
 // (weights loaded once); a wave takes 64 ions of a supercell at a time, one
 // per lane.
+template <int ACT>
 __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion, IonTables tab, MlpArgs m,
                                                     const double* ne, const double* kT, double* nu,
                                                     unsigned long long* counters, unsigned long long* fb_list)
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(BLOCK) void k_rate_mlp(GridView g, SpeciesView ion,
                     zin = Z;
                 }
             }
-            const float y = forward64(net, lane, x0, x1, zin);
+            const float y = forward64<ACT>(net, lane, x0, x1, zin);
             const bool fb = act && !inr;
             const unsigned long long fmask = __ballot(fb);
             if (fmask) {  // wave-uniform; rare
@@ -327,7 +347,12 @@ hipError_t launch_rate_mlp(const GridView& g, const SpeciesView& ion, const IonT
 {
     MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
     const int blocks = g.nsc < 1024 ? g.nsc : 1024;
-    hipLaunchKernelGGL(k_rate_mlp, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu, counters, fb_list);
+    if (ml.act == PIC_MLP_RELU)
+        hipLaunchKernelGGL(k_rate_mlp<PIC_MLP_RELU>, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu,
+                           counters, fb_list);
+    else
+        hipLaunchKernelGGL(k_rate_mlp<PIC_MLP_SILU>, dim3(blocks), dim3(BLOCK), 0, st, g, ion, tab, m, ne, kT, nu,
+                           counters, fb_list);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_rate_fallback(g, ion, tab, ne, kT, nu, gl, fb_list, counters, st);
@@ -342,6 +367,7 @@ hipError_t launch_rate_fallback(const GridView& g, const SpeciesView& ion, const
 }
 
 // ln nu of independent samples by the surrogate (exact fallback outside range).
+template <int ACT>
 __global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* kT, const double* ne, const int32_t* Zs,
                                                        IonTables tab, MlpArgs m, const double* gl, double* out)
 {
@@ -370,7 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_ln_rate_mlp(int64_t n, const double* 
                 zin = Z;
             }
         }
-        const float y = forward64(net, lane, x0, x1, zin);
+        const float y = forward64<ACT>(net, lane, x0, x1, zin);
         if (i < n) {
             if (inr) {
                 out[i] = (double)(prior + m.mu + m.s * y);
@@ -391,7 +417,12 @@ hipError_t launch_ln_rate_mlp(int64_t n, const double* kT, const double* ne, con
     MlpArgs m{ml.params, (float)ml.mu, (float)ml.s, (float)ml.t_min, (float)ml.t_max, (float)ml.n_min, (float)ml.n_max};
     int64_t blocks = (n + BLOCK - 1) / BLOCK;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_ln_rate_mlp, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, kT, ne, Z, tab, m, gl, out);
+    if (ml.act == PIC_MLP_RELU)
+        hipLaunchKernelGGL(k_ln_rate_mlp<PIC_MLP_RELU>, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, kT, ne, Z, tab,
+                           m, gl, out);
+    else
+        hipLaunchKernelGGL(k_ln_rate_mlp<PIC_MLP_SILU>, dim3((unsigned)blocks), dim3(BLOCK), 0, st, n, kT, ne, Z, tab,
+                           m, gl, out);
     return hipGetLastError();
 }
 
@@ -515,6 +546,7 @@ struct StepArgs {
     int64_t step;
 };
 
+template <int ACT>
 __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, float* grad, double* loss)
 {
     __shared__ float sW2[NH][NH + 1];                 // W2 (bf16-rounded), [out][in]
@@ -563,7 +595,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
                     const int k = 32 * s + 8 * g + j;
                     float z = sB1[k];
                     for (int q = 0; q < NIN; ++q) z = fmaf(sW1[k][q], x[q], z);
-                    const float h = bf16r(silu(z));
+                    const float h = bf16r(act_f<ACT>(z));
                     h1[s][j] = (__bf16)h;
                     h1t[wave][c][k] = h;
                 }
@@ -578,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
                 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1[1], w[1], d, 0, 0, 0);
                 for (int r = 0; r < 4; ++r) {
                     z2[t][r] = d[r] + b2v[t];
-                    y[r] = fmaf(sW3[16 * t + c], bf16r(silu(z2[t][r])), y[r]);
+                    y[r] = fmaf(sW3[16 * t + c], bf16r(act_f<ACT>(z2[t][r])), y[r]);
                 }
             }
             for (int r = 0; r < 4; ++r) {
@@ -592,12 +624,12 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
                 dy[r] = 2.0f * res * inv_b;
                 if (c == 0) lsum += (double)res * res;
             }
-            // head and layer-2 backward: dZ2[i][n] = dy_i W3[n] silu'(z2)
+            // head and layer-2 backward: dZ2[i][n] = dy_i W3[n] act'(z2)
             for (int t = 0; t < 4; ++t)
                 for (int r = 0; r < 4; ++r) {
-                    const float h2 = bf16r(silu(z2[t][r]));
+                    const float h2 = bf16r(act_f<ACT>(z2[t][r]));
                     gW3[t] = fmaf(dy[r], h2, gW3[t]);
-                    const float dz = dy[r] * sW3[16 * t + c] * dsilu(z2[t][r]);
+                    const float dz = dy[r] * sW3[16 * t + c] * dact_f<ACT>(z2[t][r]);
                     gB2[t] += dz;
                     dz2t[wave][4 * g + r][16 * t + c] = dz;
                 }
@@ -626,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
                 floatx4 d = {0.f, 0.f, 0.f, 0.f};
                 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[0], Bv[0], d, 0, 0, 0);
                 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[1], Bv[1], d, 0, 0, 0);
-                // dZ1 = dH1 silu'(z1) for samples 4g + r at unit k; dW1 / db1 partials
+                // dZ1 = dH1 act'(z1) for samples 4g + r at unit k; dW1 / db1 partials
                 const int k = 16 * tk + c;
                 float part[NIN + 1];
                 for (int q = 0; q <= NIN; ++q) part[q] = 0.0f;
@@ -636,7 +668,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
                     for (int q = 0; q < NIN; ++q) xs[q] = a.X[so * NIN + q];
                     float z1 = sB1[k];
                     for (int q = 0; q < NIN; ++q) z1 = fmaf(sW1[k][q], xs[q], z1);
-                    const float dz1 = d[r] * dsilu(z1);
+                    const float dz1 = d[r] * dact_f<ACT>(z1);
                     for (int q = 0; q < NIN; ++q) part[q] = fmaf(dz1, xs[q], part[q]);
                     part[NIN] += dz1;
                 }
@@ -690,7 +722,8 @@ hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double
     int blocks = s.batch / 16 / (BLOCK / 64);
     if (blocks > 64) blocks = 64;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_mlp_step, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
+    if (s.act == PIC_MLP_RELU) hipLaunchKernelGGL(k_mlp_step<PIC_MLP_RELU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
+    else hipLaunchKernelGGL(k_mlp_step<PIC_MLP_SILU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
     return hipGetLastError();
 }
 

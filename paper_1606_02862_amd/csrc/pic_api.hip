@@ -61,6 +61,7 @@ struct pic_ctx {
         float* grad = nullptr;
         double mu = 0.0, s = 1.0;
         double t_min = 1.0, t_max = 1e4, n_min = 1e19, n_max = 1e23;
+        int act = PIC_MLP_SILU;
         bool ready = false;
     } mlp[PIC_MAX_SPECIES];
 };
@@ -351,7 +352,7 @@ int ensure_rate_table(pic_ctx* c, int s)
 MlpLaunch mlp_launch(const pic_ctx* c, int s)
 {
     const pic_ctx::Mlp& m = c->mlp[s];
-    return MlpLaunch{m.params, m.mu, m.s, m.t_min, m.t_max, m.n_min, m.n_max};
+    return MlpLaunch{m.params, m.mu, m.s, m.t_min, m.t_max, m.n_min, m.n_max, m.act};
 }
 
 // Plasma frequency (1/s) of the reference density, SI.
@@ -1087,6 +1088,8 @@ int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_rep
     if (!(cfg->t_min_ev > 0 && cfg->t_max_ev > cfg->t_min_ev && cfg->n_min_cm3 > 0 && cfg->n_max_cm3 > cfg->n_min_cm3))
         return fail(c, PIC_ERR_ARG, "sampling ranges must be positive and increasing");
     if (!(cfg->lr > 0 && cfg->lr_final >= 0)) return fail(c, PIC_ERR_ARG, "learning rates");
+    if (cfg->activation != PIC_MLP_SILU && cfg->activation != PIC_MLP_RELU)
+        return fail(c, PIC_ERR_ARG, "activation must be PIC_MLP_SILU or PIC_MLP_RELU");
     pic_ctx::Mlp& m = c->mlp[s];
     const int64_t n = cfg->n_train;
     float* X = (float*)dev_alloc(c, (size_t)n * 8 * 4);
@@ -1113,7 +1116,7 @@ int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_rep
     const uint64_t draw_seed = (cfg->seed ^ 0x5DEECE66DULL) | 1ULL;
     double b1t = 1.0, b2t = 1.0;
     for (int it = 0; it < cfg->steps && e == hipSuccess; ++it) {
-        MlpStep ms{X, t, n, cfg->batch, draw_seed, it};
+        MlpStep ms{X, t, n, cfg->batch, draw_seed, it, cfg->activation};
         e = launch_mlp_step(m.params, ms, m.grad, losses + it, c->stream);
         b1t *= 0.9;
         b2t *= 0.999;
@@ -1134,6 +1137,7 @@ int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_rep
     if (e != hipSuccess) return fail(c, PIC_ERR_HIP, "training: %s", hipGetErrorString(e));
     m.mu = msv[0];
     m.s = msv[1];
+    m.act = cfg->activation;
     m.t_min = cfg->t_min_ev; m.t_max = cfg->t_max_ev; m.n_min = cfg->n_min_cm3; m.n_max = cfg->n_max_cm3;
     m.ready = true;
     if (out) {
@@ -1150,7 +1154,7 @@ int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_rep
     return PIC_OK;
 }
 
-int pic_mlp_get_params(pic_ctx* c, int s, float* params, double* mu_s, double* range)
+int pic_mlp_get_params(pic_ctx* c, int s, float* params, double* mu_s, double* range, int32_t* activation)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
@@ -1161,10 +1165,12 @@ int pic_mlp_get_params(pic_ctx* c, int s, float* params, double* mu_s, double* r
     }
     if (mu_s) { mu_s[0] = m.mu; mu_s[1] = m.s; }
     if (range) { range[0] = m.t_min; range[1] = m.t_max; range[2] = m.n_min; range[3] = m.n_max; }
+    if (activation) *activation = m.act;
     return PIC_OK;
 }
 
-int pic_mlp_set_params(pic_ctx* c, int s, const float* params, const double* mu_s, const double* range)
+int pic_mlp_set_params(pic_ctx* c, int s, const float* params, const double* mu_s, const double* range,
+                       int32_t activation)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
@@ -1172,6 +1178,8 @@ int pic_mlp_set_params(pic_ctx* c, int s, const float* params, const double* mu_
     for (int i = 0; i < PIC_MLP_NPARAM; ++i)
         if (!std::isfinite(params[i])) return fail(c, PIC_ERR_ARG, "non-finite parameter %d", i);
     if (!(mu_s[1] > 0) || !std::isfinite(mu_s[0])) return fail(c, PIC_ERR_ARG, "bad standardisation");
+    if (activation != PIC_MLP_SILU && activation != PIC_MLP_RELU)
+        return fail(c, PIC_ERR_ARG, "activation must be PIC_MLP_SILU or PIC_MLP_RELU");
     pic_ctx::Mlp& m = c->mlp[s];
     if (range) {
         if (!(range[0] > 0 && range[1] > range[0] && range[2] > 0 && range[3] > range[2]))
@@ -1182,6 +1190,7 @@ int pic_mlp_set_params(pic_ctx* c, int s, const float* params, const double* mu_
     HIPCHK(c, hipStreamSynchronize(c->stream));
     m.mu = mu_s[0];
     m.s = mu_s[1];
+    m.act = activation;
     m.ready = true;
     return PIC_OK;
 }
@@ -1204,7 +1213,7 @@ int pic_mlp_loss_grad(pic_ctx* c, int s, int64_t n, const float* X, const float*
     if (e == hipSuccess) e = hipMemcpyAsync(dX + n * 8, t, n * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
     if (e == hipSuccess) e = launch_zero_f64(dl, 1, c->stream);
-    MlpStep ms{dX, dX + n * 8, n, (int)n, 0, 0};
+    MlpStep ms{dX, dX + n * 8, n, (int)n, 0, 0, m.act};
     if (e == hipSuccess) e = launch_mlp_step(m.params, ms, m.grad, dl, c->stream);
     double lsum = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(grad, m.grad, PIC_MLP_NPARAM * 4, hipMemcpyDeviceToHost, c->stream);

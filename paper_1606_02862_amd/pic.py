@@ -12,6 +12,8 @@ from . import _capi as A
 
 _LAYOUT = {"uniform": 0, "shear": 1, "beams": 2}
 _MODE = {"exact": 0, "mlp": 1, "table": 2}
+_ACT = {"silu": 0, "relu": 1}  # hidden-layer activation of the rate surrogate
+_ACT_NAME = {v: k for k, v in _ACT.items()}
 
 
 def _dptr(a: np.ndarray):
@@ -190,28 +192,30 @@ class Pic:
         return out
 
     def mlp_train(self, species: int, n_train=1_000_000, batch=4096, steps=20000, lr=3e-3, lr_final=1e-5,
-                  seed=0, t_range=(1.0, 1e4), n_range=(1e19, 1e23)) -> dict:
+                  seed=0, t_range=(1.0, 1e4), n_range=(1e19, 1e23), activation="silu") -> dict:
         cfg = A.MlpTrainCfgT(n_train, batch, steps, lr, lr_final, seed, t_range[0], t_range[1], n_range[0],
-                             n_range[1])
+                             n_range[1], _ACT[activation], 0)
         rep = A.MlpReportT()
         A.check(self.lib.pic_mlp_train(self.h, species, C.byref(cfg), C.byref(rep)), self.h)
         return dict(loss_first=rep.loss_first, loss_last=rep.loss_last, mu=rep.mu, s=rep.s, train_ms=rep.train_ms,
                     steps=rep.steps)
 
     def mlp_get_params(self, species: int):
+        """(params, (mu, s), trained range, activation name)."""
         p = np.zeros(A.PIC_MLP_NPARAM, dtype=np.float32)
         mu_s = np.zeros(2)
         rng = np.zeros(4)
+        act = C.c_int32()
         A.check(self.lib.pic_mlp_get_params(self.h, species, p.ctypes.data_as(C.POINTER(C.c_float)), _dptr(mu_s),
-                                            _dptr(rng)), self.h)
-        return p, mu_s, rng
+                                            _dptr(rng), C.byref(act)), self.h)
+        return p, mu_s, rng, _ACT_NAME[act.value]
 
-    def mlp_set_params(self, species: int, params, mu_s, rng=None):
+    def mlp_set_params(self, species: int, params, mu_s, rng=None, activation="silu"):
         p = np.ascontiguousarray(params, dtype=np.float32)
         ms = np.ascontiguousarray(mu_s, dtype=np.float64)
         r = None if rng is None else np.ascontiguousarray(rng, dtype=np.float64)
         A.check(self.lib.pic_mlp_set_params(self.h, species, p.ctypes.data_as(C.POINTER(C.c_float)), _dptr(ms),
-                                            None if r is None else _dptr(r)), self.h)
+                                            None if r is None else _dptr(r), _ACT[activation]), self.h)
 
     def mlp_loss_grad(self, species: int, X, t):
         X = np.ascontiguousarray(X, dtype=np.float32)

@@ -119,7 +119,7 @@ def test_null_handles(A):
     lib = A.load()
     assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
     assert lib.pic_destroy(None) == A.PIC_OK
-    assert lib.pic_abi_version() == 4
+    assert lib.pic_abi_version() == 5
     m = A.MomentsT()
     assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
 
@@ -147,3 +147,31 @@ def test_gauss_laguerre_rule_matches_numpy(A):
     import math
     for m in range(0, 21):
         assert abs(np.sum(w * x**m) / math.factorial(m) - 1.0) < 1e-14
+
+
+def test_struct_layouts_match_the_header(A, tmp_path):
+    """Every struct the binding declares has the size and field offsets the C
+    compiler gives the header's typedef (a C program built with gcc prints
+    them), so no field is read at the wrong place."""
+    pairs = {"pic_grid_t": A.GridT, "pic_lotz_shell_t": A.LotzShellT, "pic_species_t": A.SpeciesT,
+             "pic_alloc_t": A.AllocT, "pic_moments_t": A.MomentsT, "pic_particles_view_t": A.ParticlesViewT,
+             "pic_particles64_view_t": A.ParticlesView64T, "pic_timing_t": A.TimingT,
+             "pic_ionize_stats_t": A.IonizeStatsT, "pic_mlp_train_cfg_t": A.MlpTrainCfgT,
+             "pic_mlp_report_t": A.MlpReportT}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pic.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

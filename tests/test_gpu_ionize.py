@@ -157,7 +157,8 @@ def _unflat(v):
     return d
 
 
-def test_mlp_gradient_matches_oracle_backprop(P):
+@pytest.mark.parametrize("act", ["silu", "relu"])
+def test_mlp_gradient_matches_oracle_backprop(P, act):
     cfg = _carbon_cfg((8, 8, 4))
     p = mlp.init_params(4)
     flat = _bf16(_flat(p))           # BF16-representable weights on both sides
@@ -166,9 +167,9 @@ def test_mlp_gradient_matches_oracle_backprop(P):
     X = mlp.features(T, ne, Z)
     X = _bf16(X).astype(np.float64)  # features the GPU sees exactly
     t = workloads.rng(13).normal(size=4096)
-    loss_ref, g_ref = mlp.loss_and_grad(pref, X, t)
+    loss_ref, g_ref = mlp.loss_and_grad(pref, X, t, act)
     with P.Pic(cfg) as pic:
-        pic.mlp_set_params(1, flat, [0.0, 1.0])
+        pic.mlp_set_params(1, flat, [0.0, 1.0], activation=act)
         loss, g = pic.mlp_loss_grad(1, X, t)
     gg = _unflat(g)
     _print("loss gpu/ref", loss, loss_ref)
@@ -181,7 +182,8 @@ def test_mlp_gradient_matches_oracle_backprop(P):
         assert rel < 2e-2 and cos > 0.999, k
 
 
-def test_mlp_inference_matches_oracle_forward(P):
+@pytest.mark.parametrize("act", ["silu", "relu"])
+def test_mlp_inference_matches_oracle_forward(P, act):
     """The fused inference kernel (transposed MFMA layout, augmented layer-1 K,
     head on MFMA, hidden layers in base 2) evaluates the same network as the
     oracle's plain FP64 forward.  The GPU differs by the BF16 rounding of the
@@ -189,7 +191,9 @@ def test_mlp_inference_matches_oracle_forward(P):
     W3 after the base-2 scaling (log2 e into W1, 1/log2 e into W3; relative
     2^-9 each), FP32 sums and the FP32 prior; per sample, |d ln nu| must stay
     within s times the first-order bound of those roundings propagated
-    through SiLU', W2 and W3, plus 1e-4 for the FP32 parts."""
+    through the activation's derivative (ReLU: its Lipschitz constant 1, since
+    a rounding may move a pre-activation across 0), W2 and W3, plus 1e-4 for
+    the FP32 parts."""
     cfg = _carbon_cfg((8, 8, 4))
     r = workloads.rng(31)
     p = mlp.init_params(5)
@@ -204,15 +208,16 @@ def test_mlp_inference_matches_oracle_forward(P):
     T, ne, Z = workloads.loguniform_rate_inputs(32, 50000)
     Pt, qt = workloads.CARBON_IONIZATION_EV, workloads.CARBON_LOTZ_Q
     with P.Pic(cfg) as pic:
-        pic.mlp_set_params(1, flat, [mu, s], [1.0, 1e4, 1e19, 1e23])
+        pic.mlp_set_params(1, flat, [mu, s], [1.0, 1e4, 1e19, 1e23], activation=act)
         got = pic.rate_eval("mlp", 1, T, ne, Z)
-    want = mlp.ln_rate(pref, mu, s, T, ne, Z, Pt, qt)
+    want = mlp.ln_rate(pref, mu, s, T, ne, Z, Pt, qt, act=act)
     X = mlp.features(T, ne, Z)
-    _, c = mlp.forward(pref, X)
+    _, c = mlp.forward(pref, X, act)
+    dact = mlp.dsilu if act == "silu" else np.ones_like
     dz1 = 2.0**-9 * (np.abs(X) @ np.abs(pref["W1"]).T)                       # W1 re-rounding
-    dh1 = np.abs(c["h1"]) * 2.0**-9 + np.abs(mlp.dsilu(c["z1"])) * dz1       # + activation rounding
+    dh1 = np.abs(c["h1"]) * 2.0**-9 + np.abs(dact(c["z1"])) * dz1            # + activation rounding
     dz2 = dh1 @ np.abs(pref["W2"]).T
-    bound = (np.abs(mlp.dsilu(c["z2"])) * dz2 + 2 * np.abs(c["h2"]) * 2.0**-9) @ np.abs(pref["W3"][0])  # + W3
+    bound = (np.abs(dact(c["z2"])) * dz2 + 2 * np.abs(c["h2"]) * 2.0**-9) @ np.abs(pref["W3"][0])  # + W3
     err = np.abs(got - want)
     _print("inference vs oracle: max", err.max(), "median", np.median(err), "max err/bound",
            (err / (s * bound + 1e-4)).max())
@@ -220,14 +225,15 @@ def test_mlp_inference_matches_oracle_forward(P):
     assert np.all(err <= s * 1.1 * bound + 1e-4)
 
 
-@pytest.fixture(scope="module")
-def trained(P):
-    """Train the surrogate on the GPU with the full recipe (1M samples)."""
+@pytest.fixture(scope="module", params=["silu", "relu"])
+def trained(P, request):
+    """Train the surrogate on the GPU with the full recipe (1M samples), once
+    per hidden activation."""
     cfg = _carbon_cfg((8, 8, 4))
-    tr = dict(workloads.MLP_TRAIN)
+    tr = dict(workloads.MLP_TRAIN, activation=request.param)
     pic = P.Pic(cfg)
     rep = pic.mlp_train(1, seed=workloads.MLP_TRAIN_SEED, **tr)
-    _print("training report", rep)
+    _print("training report", request.param, rep)
     yield pic, rep
     pic.close()
 
@@ -269,21 +275,27 @@ def test_mlp_out_of_range_uses_exact_fallback(trained):
 
 def test_mlp_params_roundtrip(trained):
     pic, _ = trained
-    p, ms, rng = pic.mlp_get_params(1)
+    p, ms, rng, act = pic.mlp_get_params(1)
     assert np.all(np.isfinite(p)) and ms[1] > 0
     assert tuple(rng) == (1.0, 1e4, 1e19, 1e23)
+    assert act in ("silu", "relu")
+    # a copy through set_params evaluates identically
+    T, ne, Z = workloads.loguniform_rate_inputs(44, 4096)
+    with type(pic)(_carbon_cfg((8, 8, 4))) as other:
+        other.mlp_set_params(1, p, ms, rng, act)
+        assert np.array_equal(other.rate_eval("mlp", 1, T, ne, Z), pic.rate_eval("mlp", 1, T, ne, Z))
 
 
 def test_ionize_mlp_tracks_exact(trained, P):
     """On one state, the surrogate's per-ion rates match the exact ones to the
     surrogate's accuracy, and the ionisation count to binomial noise."""
     pic_tr, _ = trained
-    params, ms, rng = pic_tr.mlp_get_params(1)
+    params, ms, rng, act = pic_tr.mlp_get_params(1)
     cfg = _carbon_cfg()
     counts = {}
     for mode in ("exact", "mlp"):
         with P.Pic(cfg) as pic:
-            pic.mlp_set_params(1, params, ms, rng)
+            pic.mlp_set_params(1, params, ms, rng, act)
             pic.step(2)
             counts[mode] = pic.ionize(mode)
     _print(counts)
@@ -299,7 +311,7 @@ def test_ionize_mlp_with_every_ion_out_of_range_equals_exact(trained, P):
     the exact step (same rates, same Philox uniforms, same decisions, same
     new electrons)."""
     pic_tr, _ = trained
-    params, ms, _ = pic_tr.mlp_get_params(1)
+    params, ms, _, act = pic_tr.mlp_get_params(1)
     cfg = _carbon_cfg()
     with P.Pic(cfg) as pic:
         s0 = _shared_carbon_state(pic, cfg, warm=2)
@@ -307,7 +319,7 @@ def test_ionize_mlp_with_every_ion_out_of_range_equals_exact(trained, P):
     for mode in ("exact", "mlp"):
         with P.Pic(cfg) as pic:
             parity.push_state(pic, s0)
-            pic.mlp_set_params(1, params, ms, [1e5, 1e6, 1e19, 1e23])  # kT < 1e5 eV everywhere
+            pic.mlp_set_params(1, params, ms, [1e5, 1e6, 1e19, 1e23], act)  # kT < 1e5 eV everywhere
             stats = pic.ionize(mode)
             out[mode] = (stats, pic.get_particles(1), pic.get_particles(0))
     se, ions_e, el_e = out["exact"]

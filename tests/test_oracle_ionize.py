@@ -144,12 +144,15 @@ def test_gauss_invariant_with_ionisation():
 # ---------------------------------------------------------------------------
 # Surrogate reference network.
 
-def test_mlp_backprop_matches_central_differences():
+@pytest.mark.parametrize("act", ["silu", "relu"])
+def test_mlp_backprop_matches_central_differences(act):
+    """Analytic gradients against central differences of the loss (ReLU: no
+    pre-activation of these seeded samples lies within h of its kink)."""
     p = mlp.init_params(3)
     T, ne, Z = workloads.loguniform_rate_inputs(5, 32)
     X = mlp.features(T, ne, Z)
     t = workloads.rng(6).normal(size=32)
-    loss, g = mlp.loss_and_grad(p, X, t)
+    loss, g = mlp.loss_and_grad(p, X, t, act)
     h = 1e-6
     r = workloads.rng(7)
     for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
@@ -157,13 +160,40 @@ def test_mlp_backprop_matches_central_differences():
         for idx in r.choice(flat.size, size=min(12, flat.size), replace=False):
             old = flat[idx]
             flat[idx] = old + h
-            lp, _ = mlp.loss_and_grad(p, X, t)
+            lp, _ = mlp.loss_and_grad(p, X, t, act)
             flat[idx] = old - h
-            lm, _ = mlp.loss_and_grad(p, X, t)
+            lm, _ = mlp.loss_and_grad(p, X, t, act)
             flat[idx] = old
             fd = (lp - lm) / (2 * h)
             an = g[name].reshape(-1)[idx]
             assert abs(fd - an) <= 1e-7 * max(1e-3, abs(an)) + 1e-10
+
+
+def test_mlp_relu_network_is_positively_homogeneous():
+    """max(a z, 0) = a max(z, 0) for a > 0: scaling W1, b1, b2 by a and W3 by
+    1/a leaves a ReLU network's output unchanged (the property that lets one
+    set of base-2 scaled inference weights serve both activations); a SiLU
+    network changes.  Its output is also piecewise linear in x0: second
+    differences vanish where no unit switches."""
+    p = mlp.init_params(11)
+    T, ne, Z = workloads.loguniform_rate_inputs(12, 64)
+    X = mlp.features(T, ne, Z)
+    a = 1.4426950408889634
+    q = dict(p, W1=p["W1"] * a, b1=p["b1"] * a, b2=p["b2"] * a, W3=p["W3"] / a)
+    y0, _ = mlp.forward(p, X, "relu")
+    y1, _ = mlp.forward(q, X, "relu")
+    assert np.max(np.abs(y1 - y0)) < 1e-13 * max(1.0, np.max(np.abs(y0)))
+    s0, _ = mlp.forward(p, X, "silu")
+    s1, _ = mlp.forward(q, X, "silu")
+    assert np.max(np.abs(s1 - s0)) > 1e-3
+    d = 1e-4
+    Xs = [X.copy() for _ in range(3)]
+    for k, Xk in enumerate(Xs):
+        Xk[:, 0] += (k - 1) * d
+    (ym, c0), (yc, c1), (yp, c2) = (mlp.forward(p, Xk, "relu") for Xk in Xs)
+    same = np.all((c0["z1"] > 0) == (c2["z1"] > 0), axis=1) & np.all((c0["z2"] > 0) == (c2["z2"] > 0), axis=1)
+    assert same.sum() > 50
+    assert np.max(np.abs((yp - 2 * yc + ym)[same])) < 1e-11
 
 
 def test_prior_residual_is_bounded_by_e1_inequalities():

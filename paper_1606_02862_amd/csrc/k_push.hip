@@ -54,6 +54,42 @@ struct Tile {
     static constexpr int SMEM = 6 * GN * (int)sizeof(R) + 3 * JN * 8;
 };
 
+// PCS keeps only what its stencils reach, which halves its LDS and lets two
+// workgroups share a CU (for CIC and TSC the same trimming measured 1-2 %
+// slower than the full boxes above, which they keep).  Field components share
+// the row and plane pitch of the full box; along z a component on the nodes
+// needs planes [-1, SZ + 1] and one staggered by half a cell (E_z, B_x, B_y)
+// [-2, SZ + 1].  Element (x, y, z) of component c is at
+// fbase(c) + ((z + GL) GY + y + GL) GX + x + GL.  The current tile takes nodes
+// [-2, S + 2] per axis (the deposit window's first node never lies below -2)
+// and J_z one plane less along z.
+template <int D = 0>  // a template so that its constants may use its own functions
+struct PcsTileT {
+    using T = Tile<3>;
+    static constexpr int GL = T::GL, GX = T::GX, GY = T::GY;
+    static constexpr bool zstag(int c) { return c == 2 || c == 3 || c == 4; }
+    static constexpr int zlo(int c) { return zstag(c) ? -2 : -1; }
+    static constexpr int zn(int c) { return zstag(c) ? SZ + 4 : SZ + 3; }
+    static constexpr int foff(int c) { return c == 0 ? 0 : foff(c - 1) + zn(c - 1) * GX * GY; }
+    static constexpr int fbase(int c) { return foff(c) - (zlo(c) + GL) * GX * GY; }
+    static constexpr int FN = foff(6);
+    static constexpr int JL = 2;
+    static constexpr int JX = SX + 2 * JL + 1, JY = SY + 2 * JL + 1, JZ = SZ + 2 * JL + 1;
+    static constexpr int JN = JX * JY * JZ;  // a full component box (J_x, J_y)
+    static constexpr int jz(int c) { return c == 2 ? JZ - 1 : JZ; }
+    static constexpr int joff(int c) { return c == 0 ? 0 : joff(c - 1) + jz(c - 1) * JX * JY; }
+    static constexpr int JNT = joff(3);
+    // the 64-bit current tile at a 16-byte aligned offset (natural alignment
+    // of its 64-bit atomics, loads and stores)
+    template <class R> static constexpr int fbytes() { return (FN * (int)sizeof(R) + 15) / 16 * 16; }
+    template <class R> static constexpr int smem() { return fbytes<R>() + JNT * 8; }
+};
+using PcsTile = PcsTileT<>;
+template <int ORDER, class R> constexpr int smem_bytes()
+{
+    return ORDER == 3 ? PcsTile::smem<R>() : Tile<ORDER, R>::SMEM;
+}
+
 // Largest arrival list the particle kernel can absorb in its LDS scratch.
 __host__ __device__ constexpr int max_cap_in(int order)
 {
@@ -61,7 +97,7 @@ __host__ __device__ constexpr int max_cap_in(int order)
 }
 static_assert(3 * 2048 + 64 <= Tile<1>::SMEM / 4, "CIC scratch");
 static_assert(3 * 4096 + 128 <= Tile<2>::SMEM / 4, "TSC scratch");
-static_assert(3 * 4096 + 128 <= Tile<3>::SMEM / 4, "PCS scratch");
+static_assert(3 * 4096 + 128 <= PcsTile::smem<float>() / 4, "PCS scratch");
 
 // Current-tile accumulator: 64-bit fixed point for FP32, FP64 for FP64.
 template <class R>
@@ -158,14 +194,17 @@ __device__ inline void deposit(A* tJ, int mx, int my, int mz, const R* S0x, cons
     for (int k = 1; k < W - 1; ++k) {
         Rx[k] = Rx[k - 1] + DSx[k]; Ry[k] = Ry[k - 1] + DSy[k]; Rz[k] = Rz[k - 1] + DSz[k];
     }
+    // PCS: the trimmed current tile (PcsTile), same origin in every component
+    constexpr bool PCS = ORDER == 3;
+    constexpr int TJX = PCS ? PcsTile::JX : T::JX, TJY = PCS ? PcsTile::JY : T::JY;
     A* Jx = tJ;
-    A* Jy = tJ + T::JN;
-    A* Jz = tJ + 2 * T::JN;
+    A* Jy = tJ + (PCS ? PcsTile::joff(1) : T::JN);
+    A* Jz = tJ + (PCS ? PcsTile::joff(2) : 2 * T::JN);
 #pragma unroll
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int b = 0; b < W; ++b) {
-            const int row = ((mz + c) * T::JY + (my + b)) * T::JX + mx;
+            const int row = ((mz + c) * TJY + (my + b)) * TJX + mx;
             const R ax = cx * rfma(Py[b], S0z[c], Qy[b] * DSz[c]);
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) jadd(&Jx[row + a], ax * Rx[a]);
@@ -176,7 +215,7 @@ __device__ inline void deposit(A* tJ, int mx, int my, int mz, const R* S0x, cons
         for (int a = 0; a < W; ++a) {
             const R ay = cy * rfma(Pz[c], S0x[a], Qz[c] * DSx[a]);
 #pragma unroll
-            for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], ay * Ry[b]);
+            for (int b = 0; b < W - 1; ++b) jadd(&Jy[((mz + c) * TJY + (my + b)) * TJX + (mx + a)], ay * Ry[b]);
         }
 #pragma unroll
     for (int b = 0; b < W; ++b)
@@ -184,7 +223,7 @@ __device__ inline void deposit(A* tJ, int mx, int my, int mz, const R* S0x, cons
         for (int a = 0; a < W; ++a) {
             const R az = cz * rfma(Px[a], S0y[b], Qx[a] * DSy[b]);
 #pragma unroll
-            for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * T::JY + (my + b)) * T::JX + (mx + a)], az * Rz[c]);
+            for (int c = 0; c < W - 1; ++c) jadd(&Jz[((mz + c) * TJY + (my + b)) * TJX + (mx + a)], az * Rz[c]);
         }
 }
 
@@ -212,10 +251,13 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     using A = JAcc<R>;
     using R4 = typename Vec4<R>::type;
     constexpr unsigned RB = sizeof(R);
-    __shared__ __align__(16) unsigned char smem[T::SMEM];
+    constexpr bool PCS = ORDER == 3;  // PCS uses the trimmed tiles of PcsTile
+    constexpr int JL = PCS ? PcsTile::JL : T::JL;
+    __shared__ __align__(16) unsigned char smem[smem_bytes<ORDER, R>()];
     R(*fE)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem);
     R(*fB)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem + 3 * T::GN * RB);
-    A* tJ = reinterpret_cast<A*>(smem + 6 * T::GN * RB);
+    R* const F = reinterpret_cast<R*>(smem);  // PCS: the six boxes at PcsTile::fbase
+    A* tJ = reinterpret_cast<A*>(smem + (PCS ? PcsTile::fbytes<R>() : 6 * T::GN * RB));
     __shared__ int s_holes, s_queue, s_cnt[3];
     // FP32 CIC: each wave appends its queued particles to a region of its own
     // (no LDS atomic, and no wait on one, inside the frame loop); measured 1 %
@@ -241,13 +283,21 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
         gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
         const int gi = gx + g.nx * (gy + g.ny * gz);
+        if constexpr (PCS) {  // each component keeps the planes its stencil reaches
+            const int z = tz - T::GL;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            fE[c][t] = g.E[c * N + gi];
-            fB[c][t] = g.B[c * N + gi];
+            for (int c = 0; c < 6; ++c)
+                if (z >= PcsTile::zlo(c) && z < PcsTile::zlo(c) + PcsTile::zn(c))
+                    F[PcsTile::fbase(c) + t] = c < 3 ? g.E[c * N + gi] : g.B[(c - 3) * N + gi];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fE[c][t] = g.E[c * N + gi];
+                fB[c][t] = g.B[c * N + gi];
+            }
         }
     }
-    for (int t = tid; t < 3 * T::JN; t += NT) tJ[t] = A(0);
+    for (int t = tid; t < (PCS ? PcsTile::JNT : 3 * T::JN); t += NT) tJ[t] = A(0);
     if (tid == 0) { s_holes = 0; s_queue = 0; }
     __syncthreads();
     const int wave = tid >> 6;
@@ -316,12 +366,22 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         // differ from it by one node at most per axis and lie in the tile
         const int bn = ((inz + T::GL) * T::GY + (iny + T::GL)) * T::GX + (inx + T::GL);
         const int ox_ = isx - inx, oy_ = (isy - iny) * T::GX, oz_ = (isz - inz) * (T::GX * T::GY);
-        const R Ex = interp_n<ORDER, Q, P, P>(&fE[0][bn + ox_], wsx, wny, wnz);
-        const R Ey = interp_n<ORDER, P, Q, P>(&fE[1][bn + oy_], wnx, wsy, wnz);
-        const R Ez = interp_n<ORDER, P, P, Q>(&fE[2][bn + oz_], wnx, wny, wsz);
-        const R Bx = interp_n<ORDER, P, Q, Q>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
-        const R By = interp_n<ORDER, Q, P, Q>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
-        const R Bz = interp_n<ORDER, Q, Q, P>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
+        R Ex, Ey, Ez, Bx, By, Bz;
+        if constexpr (PCS) {
+            Ex = interp_n<ORDER, Q, P, P>(&F[PcsTile::fbase(0) + bn + ox_], wsx, wny, wnz);
+            Ey = interp_n<ORDER, P, Q, P>(&F[PcsTile::fbase(1) + bn + oy_], wnx, wsy, wnz);
+            Ez = interp_n<ORDER, P, P, Q>(&F[PcsTile::fbase(2) + bn + oz_], wnx, wny, wsz);
+            Bx = interp_n<ORDER, P, Q, Q>(&F[PcsTile::fbase(3) + bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
+            By = interp_n<ORDER, Q, P, Q>(&F[PcsTile::fbase(4) + bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
+            Bz = interp_n<ORDER, Q, Q, P>(&F[PcsTile::fbase(5) + bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
+        } else {
+            Ex = interp_n<ORDER, Q, P, P>(&fE[0][bn + ox_], wsx, wny, wnz);
+            Ey = interp_n<ORDER, P, Q, P>(&fE[1][bn + oy_], wnx, wsy, wnz);
+            Ez = interp_n<ORDER, P, P, Q>(&fE[2][bn + oz_], wnx, wny, wsz);
+            Bx = interp_n<ORDER, P, Q, Q>(&fB[0][bn + oy_ + oz_], wnx, wsy, wsz) + g.b0x;
+            By = interp_n<ORDER, Q, P, Q>(&fB[1][bn + ox_ + oz_], wsx, wny, wsz) + g.b0y;
+            Bz = interp_n<ORDER, Q, Q, P>(&fB[2][bn + ox_ + oy_], wsx, wsy, wnz) + g.b0z;
+        }
 
         // ---- relativistic Boris: half kick, rotation, half kick
         const R h = q * qm;
@@ -373,7 +433,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
                 DSy[k] = w1y[k] - wny[k];
                 DSz[k] = w1z[k] - wnz[k];
             }
-            deposit<ORDER, T::NP>(tJ, inx + T::JL, iny + T::JL, inz + T::JL, wnx, DSx, wny, DSy, wnz, DSz,
+            deposit<ORDER, T::NP>(tJ, inx + JL, iny + JL, inz + JL, wnx, DSx, wny, DSy, wnz, DSz,
                                   jcx * qw, jcy * qw, jcz * qw);
         }
         // queue the others (contiguous slots per wave from one LDS atomic);
@@ -451,9 +511,9 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         const R x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
         const R x1 = b.x, y1 = b.y, z1 = b.z;
         R S0x[T::W], DSx[T::W], S0y[T::W], DSy[T::W], S0z[T::W], DSz[T::W];
-        const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + T::JL;
-        const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + T::JL;
-        const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + T::JL;
+        const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + JL;
+        const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + JL;
+        const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + JL;
         deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw);
     }
 
@@ -489,21 +549,43 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     __syncthreads();
 
     // ---- flush the current tile (guards overlap neighbouring supercells)
-    for (int t = tid; t < T::JN; t += NT) {
-        const int tx = t % T::JX, ty = (t / T::JX) % T::JY, tz = t / (T::JX * T::JY);
-        int gx = ox + tx - T::JL, gy = oy + ty - T::JL, gz = oz + tz - T::JL;
-        gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
-        gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
-        gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
-        const int gi = gx + g.nx * (gy + g.ny * gz);
+    if constexpr (PCS) {
+        for (int t = tid; t < PcsTile::JN; t += NT) {  // the J_x / J_y box; J_z has one plane less
+            const int tx = t % PcsTile::JX, ty = (t / PcsTile::JX) % PcsTile::JY, tz = t / (PcsTile::JX * PcsTile::JY);
+            int gx = ox + tx - JL, gy = oy + ty - JL, gz = oz + tz - JL;
+            gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
+            gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
+            gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
+            const int gi = gx + g.nx * (gy + g.ny * gz);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if constexpr (std::is_same<R, float>::value) {
-                const long long iv = (long long)tJ[c * T::JN + t];
-                if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
-            } else {
-                const double v = tJ[c * T::JN + t];
-                if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
+            for (int c = 0; c < 3; ++c) {
+                if (tz >= PcsTile::jz(c)) continue;
+                if constexpr (std::is_same<R, float>::value) {
+                    const long long iv = (long long)tJ[PcsTile::joff(c) + t];
+                    if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+                } else {
+                    const double v = tJ[PcsTile::joff(c) + t];
+                    if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
+                }
+            }
+        }
+    } else {
+        for (int t = tid; t < T::JN; t += NT) {
+            const int tx = t % T::JX, ty = (t / T::JX) % T::JY, tz = t / (T::JX * T::JY);
+            int gx = ox + tx - T::JL, gy = oy + ty - T::JL, gz = oz + tz - T::JL;
+            gx += (gx < 0) ? g.nx : 0; gx -= (gx >= g.nx) ? g.nx : 0;
+            gy += (gy < 0) ? g.ny : 0; gy -= (gy >= g.ny) ? g.ny : 0;
+            gz += (gz < 0) ? g.nz : 0; gz -= (gz >= g.nz) ? g.nz : 0;
+            const int gi = gx + g.nx * (gy + g.ny * gz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if constexpr (std::is_same<R, float>::value) {
+                    const long long iv = (long long)tJ[c * T::JN + t];
+                    if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+                } else {
+                    const double v = tJ[c * T::JN + t];
+                    if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
+                }
             }
         }
     }

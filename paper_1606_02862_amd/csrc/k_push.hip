@@ -1,4 +1,5 @@
-// The particle kernel: per supercell, field gather (CIC/TSC on the Yee grid),
+// The particle kernel: per supercell, field gather (CIC, TSC or PCS on the Yee
+// grid, standard or Galerkin),
 // relativistic Boris push, move, and Esirkepov charge-conserving current
 // deposition, fused in one pass over the supercell's frames.
 //
@@ -27,7 +28,8 @@
 // node is unchanged on all three axes (it stays in its cell for CIC, keeps its
 // nearest node for TSC) needs only an (ORDER+1)-node window per axis, which
 // is done in line (CIC: 12 atomics instead of 54).  The others are queued in
-// a per-supercell scratch list (wave ballot + popcount for the slots) and
+// a per-supercell scratch list (wave ballot + popcount for the slots; for CIC
+// each wave owns a region of it, so no LDS counter is needed) and
 // deposited after the frame loop with the full (ORDER+2)-node window, so that
 // no wave runs the wide window for a few of its lanes.
 #include <type_traits>

@@ -242,6 +242,22 @@ __device__ inline const E& at(const E* base, unsigned byte_off)
     return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
+// Particle streams of the frame loop (read once, written once per step):
+// with STREAM the loads and stores carry the non-temporal hint.  Measured
+// about 1 % faster for CIC and slightly slower for TSC, so only CIC sets it.
+template <bool STREAM, typename E>
+__device__ inline E ld_part(const E* base, unsigned byte_off)
+{
+    if constexpr (STREAM) return __builtin_nontemporal_load(&at(base, byte_off));
+    else return at(base, byte_off);
+}
+template <bool STREAM, typename E>
+__device__ inline void st_part(E* base, unsigned byte_off, E v)
+{
+    if constexpr (STREAM) __builtin_nontemporal_store(v, &at(base, byte_off));
+    else at(base, byte_off) = v;
+}
+
 // Waves per SIMD the register budget is fitted to: 4 in FP32, 2 in FP64.
 template <class R> constexpr int push_waves() { return std::is_same<R, float>::value ? 4 : 2; }
 
@@ -254,6 +270,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     using R4 = typename Vec4<R>::type;
     constexpr unsigned RB = sizeof(R);
     constexpr bool PCS = ORDER == 3;  // PCS uses the trimmed tiles of PcsTile
+    constexpr bool STREAM = ORDER == 1 && std::is_same<R, float>::value;
     constexpr int JL = PCS ? PcsTile::JL : T::JL;
     __shared__ __align__(16) unsigned char smem[smem_bytes<ORDER, R>()];
     R(*fE)[T::GN] = reinterpret_cast<R(*)[T::GN]>(smem);
@@ -350,8 +367,9 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
             // obscures the order of these loads relative to this iteration's stores
             const int sn = slot + NT < n ? slot + NT : n - 1;
             const unsigned un = RB * (unsigned)sn;
-            nx0 = at(px, un); ny0 = at(py, un); nz0 = at(pz, un);
-            nux = at(pux, un); nuy = at(puy, un); nuz = at(puz, un); nw = at(pw, un);
+            nx0 = ld_part<STREAM>(px, un); ny0 = ld_part<STREAM>(py, un); nz0 = ld_part<STREAM>(pz, un);
+            nux = ld_part<STREAM>(pux, un); nuy = ld_part<STREAM>(puy, un); nuz = ld_part<STREAM>(puz, un);
+            nw = ld_part<STREAM>(pw, un);
             if constexpr (HAS_Z) nzs = pzs[sn];
         }
 
@@ -462,8 +480,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         // ---- store in place; a particle that left the supercell keeps its
         // unshifted position here and its slot goes on the hole list, handed
         // over after the frame loop so no wave waits on a global atomic here
-        at(px, u) = x1; at(py, u) = y1; at(pz, u) = z1;
-        at(pux, u) = ux; at(puy, u) = uy; at(puz, u) = uz;
+        st_part<STREAM>(px, u, x1); st_part<STREAM>(py, u, y1); st_part<STREAM>(pz, u, z1);
+        st_part<STREAM>(pux, u, ux); st_part<STREAM>(puy, u, uy); st_part<STREAM>(puz, u, uz);
         const bool left = (x1 < R(0)) || (x1 >= (R)SX) || (y1 < R(0)) || (y1 >= (R)SY) || (z1 < R(0)) ||
                           (z1 >= (R)SZ);
         const unsigned long long lmask = __ballot(left);

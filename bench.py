@@ -242,6 +242,8 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     zz = np.full(lt.size, 2, dtype=np.int32)
     rl = np.abs(np.expm1(pic.rate_eval("mlp", 1, lt, ln, zz) - pic.rate_eval("exact", 1, lt, ln, zz)))
     out["mlp_error_live_cells_Z2"] = stats(rl)
+    rr = np.abs(np.expm1(pic_relu.rate_eval("mlp", 1, lt, ln, zz) - pic.rate_eval("exact", 1, lt, ln, zz)))
+    out["mlp_relu_error_live_cells_Z2"] = stats(rr)
     pic.close()
     pic_relu.close()
     if cpu:

@@ -143,6 +143,11 @@ def load() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1606_02862_amd.build.build()")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; whichever is loaded first serves the whole process.  Load torch
+        # first so the library binds the runtime torch's streams and allocator
+        # live in (the other order leaves pinned host allocations failing).
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

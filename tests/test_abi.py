@@ -132,6 +132,22 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         _capi.load()
 
 
+def test_load_brings_in_torch_first(A):
+    # torch's bundled HIP runtime and the system one share a soname, so the
+    # library must be opened after torch in a fresh process; otherwise the
+    # two sides bind different runtimes
+    import subprocess
+    import sys
+    code = ("import sys; import paper_1606_02862_amd as P; assert 'torch' not in sys.modules; "
+            "P.load(); assert 'torch' in sys.modules; "
+            "m = [l for l in open('/proc/self/maps') if 'libamdhip64' in l]; "
+            "print(len({l.split()[-1] for l in m}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip() == "1"  # exactly one HIP runtime mapped
+
+
 def test_gauss_laguerre_rule_matches_numpy(A):
     """The library's own Golub-Welsch rule (host code) against numpy's laggauss."""
     import numpy as np

@@ -142,8 +142,7 @@ def test_load_brings_in_torch_first(A):
             "P.load(); assert 'torch' in sys.modules; "
             "m = [l for l in open('/proc/self/maps') if 'libamdhip64' in l]; "
             "print(len({l.split()[-1] for l in m}))")
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip() == "1"  # exactly one HIP runtime mapped
 

@@ -10,7 +10,7 @@ __global__ __launch_bounds__(BLOCK) void k_migrate(GridViewT<R> g, SpeciesViewT<
 {
     extern __shared__ int lds[];
     __shared__ int counters[3];
-    const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
+    const int sc = sc_of_block(blockIdx.x, g.nsc, g.ncx * g.ncy, g.xcd_remap);
     fill_supercell<BLOCK>(g, s, sc, par, lds, counters);
 }
 

@@ -285,7 +285,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     constexpr int NW = NT / 64;
     __shared__ int s_qn[NW];
 
-    const int sc = sc_of_block(blockIdx.x, g.nsc, g.xcd_remap);
+    const int sc = sc_of_block(blockIdx.x, g.nsc, g.ncx * g.ncy, g.xcd_remap);
     // arrivals of the previous step first (frames dense again before pushing)
     if (apar >= 0) fill_supercell<NT>(g, s, sc, apar, reinterpret_cast<int*>(smem), s_cnt);
     const int tid = threadIdx.x;

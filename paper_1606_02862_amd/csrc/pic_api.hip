@@ -692,7 +692,10 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
     g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
     g.ncx = grid->nx / SX; g.ncy = grid->ny / SY; g.ncz = grid->nz / SZ;
     g.nsc = g.ncx * g.ncy * g.ncz;
-    g.xcd_remap = (g.nsc % 8 == 0) ? 1 : 0;
+    {   // z-fastest slabs when each XCD's share is whole z-layers, plain slabs otherwise
+        const int per = g.nsc / 8, nxy = g.ncx * g.ncy;
+        g.xcd_remap = (g.nsc % 8 != 0) ? 0 : (per % nxy == 0) ? per / nxy : 1;
+    }
     g.dx = (float)grid->dx; g.dy = (float)grid->dy; g.dz = (float)grid->dz; g.dt = (float)grid->dt;
     g.b0x = (float)grid->b0[0]; g.b0y = (float)grid->b0[1]; g.b0z = (float)grid->b0[2];
     c->fp64 = grid->precision == PIC_PRECISION_FP64;

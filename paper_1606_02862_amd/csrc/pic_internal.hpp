@@ -34,7 +34,7 @@ struct GridViewT {
     int nx, ny, nz;        // cells
     int ncx, ncy, ncz;     // supercells per axis
     int nsc;               // number of supercells
-    int xcd_remap;         // 1: map blockIdx so each XCD gets a contiguous slab
+    int xcd_remap;         // block -> supercell order (sc_of_block): 0 identity, L >= 1 XCD slabs of L z-layers
     R dx, dy, dz, dt;
     R b0x, b0y, b0z;
     R* E;                  // 3 * N, component-major, x fastest
@@ -87,13 +87,17 @@ struct Species {
 };
 
 // Map a workgroup index to a supercell so that the 8 XCDs (which receive
-// workgroups round-robin) each work on one contiguous slab of supercells and
-// share its guard cells in their own L2.
-__host__ __device__ inline int sc_of_block(int b, int nsc, int remap)
+// workgroups round-robin) each work on one contiguous slab of nsc/8
+// supercells and share its guard cells in their own L2.  remap = 0: the
+// identity; remap = L >= 1: the slab is L whole z-layers of nxy = ncx*ncy
+// supercells (L = 1 also stands for a slab that is not), and within it the
+// blocks walk z fastest, so that the neighbours of a supercell along every
+// axis, not only x and y, run at about the same time.
+__host__ __device__ inline int sc_of_block(int b, int nsc, int nxy, int remap)
 {
     if (!remap) return b;
-    const int per = nsc >> 3;
-    return (b & 7) * per + (b >> 3);
+    const int per = nsc >> 3, i = b >> 3;
+    return (b & 7) * per + (i % remap) * nxy + i / remap;
 }
 
 // ---------------------------------------------------------------- launchers

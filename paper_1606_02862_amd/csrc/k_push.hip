@@ -229,6 +229,80 @@ __device__ inline void deposit(A* tJ, int mx, int my, int mz, const R* S0x, cons
         }
 }
 
+// Esirkepov deposit of a particle whose first shape node changed along one
+// axis only (ax = 0, 1, 2 for x, y, z).  Along the two other axes the
+// general window's last node has zero weight, so they take ORDER + 1 nodes:
+// for CIC 8 + 6 + 6 atomics instead of 3 x 18.  The axes are relabelled per
+// lane, a = ax, b = ax + 1, c = ax + 2 (mod 3), with the tile strides and
+// current components following, so lanes that crossed along different axes
+// share every instruction.  The terms are those of deposit(); the transverse
+// factor of J_b is written as P_a S0_c + Q_a DS_c, the same sum.
+template <int ORDER, class R, class A>
+__device__ inline void deposit_cross1(A* tJ, int ax, int mx, int my, int mz, const R* S0x, const R* DSx,
+                                      const R* S0y, const R* DSy, const R* S0z, const R* DSz, R cx, R cy, R cz)
+{
+    using T = Tile<ORDER>;
+    constexpr int W = T::W, NP = T::NP;
+    const bool ix = ax == 0, iy = ax == 1;
+    R S0a[W], DSa[W], S0b[NP], DSb[NP], S0c[NP], DSc[NP];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        S0a[k] = ix ? S0x[k] : iy ? S0y[k] : S0z[k];
+        DSa[k] = ix ? DSx[k] : iy ? DSy[k] : DSz[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        S0b[k] = ix ? S0y[k] : iy ? S0z[k] : S0x[k];
+        DSb[k] = ix ? DSy[k] : iy ? DSz[k] : DSx[k];
+        S0c[k] = ix ? S0z[k] : iy ? S0x[k] : S0y[k];
+        DSc[k] = ix ? DSz[k] : iy ? DSx[k] : DSy[k];
+    }
+    const R ca = ix ? cx : iy ? cy : cz, cb = ix ? cy : iy ? cz : cx, cc = ix ? cz : iy ? cx : cy;
+    constexpr int PX = 1, PY = T::JX, PZ = T::JX * T::JY;  // tile strides
+    const int sa = ix ? PX : iy ? PY : PZ, sb = ix ? PY : iy ? PZ : PX, sc = ix ? PZ : iy ? PX : PY;
+    A* const Ja = tJ + (ix ? 0 : iy ? 1 : 2) * T::JN;
+    A* const Jb = tJ + (ix ? 1 : iy ? 2 : 0) * T::JN;
+    A* const Jc = tJ + (ix ? 2 : iy ? 0 : 1) * T::JN;
+    const int o = mx * PX + my * PY + mz * PZ;
+    const R third = R(1) / R(3);
+    const R half = R(0.5);
+    R Pa[W], Qa[W], Pb[NP], Qb[NP];
+#pragma unroll
+    for (int k = 0; k < W; ++k) { Pa[k] = rfma(half, DSa[k], S0a[k]); Qa[k] = rfma(third, DSa[k], half * S0a[k]); }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) { Pb[k] = rfma(half, DSb[k], S0b[k]); Qb[k] = rfma(third, DSb[k], half * S0b[k]); }
+    R Ra[W - 1], Rb[NP - 1], Rc[NP - 1];  // running sums of DS
+    Ra[0] = DSa[0]; Rb[0] = DSb[0]; Rc[0] = DSc[0];
+#pragma unroll
+    for (int k = 1; k < W - 1; ++k) Ra[k] = Ra[k - 1] + DSa[k];
+#pragma unroll
+    for (int k = 1; k < NP - 1; ++k) { Rb[k] = Rb[k - 1] + DSb[k]; Rc[k] = Rc[k - 1] + DSc[k]; }
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            const R v = ca * rfma(Pb[b], S0c[c], Qb[b] * DSc[c]);
+#pragma unroll
+            for (int a = 0; a < W - 1; ++a) jadd(&Ja[o + c * sc + b * sb + a * sa], v * Ra[a]);
+        }
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const R v = cb * rfma(Pa[a], S0c[c], Qa[a] * DSc[c]);
+#pragma unroll
+            for (int b = 0; b < NP - 1; ++b) jadd(&Jb[o + c * sc + b * sb + a * sa], v * Rb[b]);
+        }
+#pragma unroll
+    for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const R v = cc * rfma(Pa[a], S0b[b], Qa[a] * DSb[b]);
+#pragma unroll
+            for (int c = 0; c < NP - 1; ++c) jadd(&Jc[o + c * sc + b * sb + a * sa], v * Rc[c]);
+        }
+}
+
 // Element at a 32-bit byte offset from a block-uniform base: lets the compiler
 // use the scalar-base + 32-bit-offset global addressing form.
 template <typename E>
@@ -283,7 +357,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     // faster for CIC and 2-3 % slower for TSC, which keeps the shared queue
     constexpr bool WAVEQ = std::is_same<R, float>::value && ORDER == 1;
     constexpr int NW = NT / 64;
-    __shared__ int s_qn[NW];
+    __shared__ int s_qn[NW], s_qo[NW];
 
     const int sc = sc_of_block(blockIdx.x, g.nsc, g.ncx * g.ncy, g.xcd_remap);
     // arrivals of the previous step first (frames dense again before pushing)
@@ -321,7 +395,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     __syncthreads();
     const int wave = tid >> 6;
     const int rw = g.qcap / NW;  // queue region of one wave: >= its slots of every frame
-    int qn = 0;                  // records this wave has queued (the same in all its active lanes)
+    int qn = 0;                  // records this wave has queued (the same in all its active lanes):
+    int qo = 0;                  // qn single-axis crossers from the front of its region, qo others from the back
 
     const int n = s.count[sc];
     const int64_t base = (int64_t)sc * s.cap;
@@ -456,24 +531,36 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
             deposit<ORDER, T::NP>(tJ, inx + JL, iny + JL, inz + JL, wnx, DSx, wny, DSy, wnz, DSz,
                                   jcx * qw, jcy * qw, jcz * qw);
         }
-        // queue the others (contiguous slots per wave from one LDS atomic);
-        // one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 -
+        // queue the others; one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 s,
+        // s the axis of a single-axis crossing in the per-wave queues, -1 for the others there
         const unsigned long long qmask = __ballot(!same);
         if (qmask) {
-            int qb;
-            if constexpr (WAVEQ) {
-                qb = wave * rw + qn;
-                qn += __popcll(qmask);
-            } else {
+            if constexpr (WAVEQ) {  // the wave's own region, crossers of one axis first
+                const unsigned long long below = (1ull << lane) - 1ull;
+                const int nax = (fx1 != inx) + (fy1 != iny) + (fz1 != inz);
+                const unsigned long long smask = __ballot(nax == 1);
+                const unsigned long long mmask = qmask & ~smask;
+                if (!same) {
+                    const bool one = nax == 1;
+                    const int slot = one ? wave * rw + qn + __popcll(smask & below)
+                                         : wave * rw + rw - 1 - (qo + __popcll(mmask & below));
+                    const R ax = one ? R(fx1 != inx ? 0 : fy1 != iny ? 1 : 2) : R(-1);
+                    R4* e = g.qbuf + 2 * (qbase + slot);
+                    e[0] = make4(x0, y0, z0, qw);
+                    e[1] = make4(x1, y1, z1, ax);
+                }
+                qn += __popcll(smask);
+                qo += __popcll(mmask);
+            } else {  // contiguous slots per wave from one LDS atomic
                 const int leader = __ffsll((long long)qmask) - 1;
-                qb = 0;
+                int qb = 0;
                 if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
                 qb = __shfl(qb, leader, 64);
-            }
-            if (!same) {
-                R4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
-                e[0] = make4(x0, y0, z0, qw);
-                e[1] = make4(x1, y1, z1, R(0));
+                if (!same) {
+                    R4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
+                    e[0] = make4(x0, y0, z0, qw);
+                    e[1] = make4(x1, y1, z1, R(0));
+                }
             }
         }
 
@@ -507,25 +594,11 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
     }
     if (bad) g.flags[FLAG_CFL] = 1;
     // lane 0 of a wave takes part in every frame its wave does, so it holds the count
-    if (WAVEQ && lane == 0) s_qn[wave] = qn;
+    if (WAVEQ && lane == 0) { s_qn[wave] = qn; s_qo[wave] = qo; }
     __syncthreads();
 
-    // ---- queued particles: general (ORDER+2)-node window, all lanes busy
-    int qpre[NW];  // per-wave queues: first queue index of each wave's records
-    int nq = 0;
-    if constexpr (WAVEQ) {
-#pragma unroll
-        for (int w = 0; w < NW; ++w) { qpre[w] = nq; nq += s_qn[w]; }
-    } else {
-        nq = s_queue;
-    }
-    for (int t = tid; t < nq; t += NT) {
-        int rec = t;
-        if constexpr (WAVEQ) {  // the last wave whose first index is <= t (waves may queue none)
-#pragma unroll
-            for (int k = 1; k < NW; ++k)
-                if (t >= qpre[k]) rec = k * rw + (t - qpre[k]);
-        }
+    // ---- queued particles, all lanes busy
+    auto queued = [&](int rec, bool one) {
         const R4* e = g.qbuf + 2 * (qbase + rec);
         const R4 a = e[0], b = e[1];
         const R x0 = a.x, y0 = a.y, z0 = a.z, qw = a.w;
@@ -534,7 +607,36 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
         const int mx = esirkepov_axis<ORDER>(x0, x1, S0x, DSx) + JL;
         const int my = esirkepov_axis<ORDER>(y0, y1, S0y, DSy) + JL;
         const int mz = esirkepov_axis<ORDER>(z0, z1, S0z, DSz) + JL;
-        deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw);
+        if (WAVEQ && one) {  // only the per-wave queues (FP32 CIC) hold single-axis records
+            const int ax = min(max((int)b.w, 0), 2);
+            deposit_cross1<ORDER>(tJ, ax, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw);
+        } else {
+            deposit<ORDER, T::W>(tJ, mx, my, mz, S0x, DSx, S0y, DSy, S0z, DSz, jcx * qw, jcy * qw, jcz * qw);
+        }
+    };
+    if constexpr (WAVEQ) {
+        // single-axis crossers (front of each wave's region), then the others (back)
+        int qpre[NW], mpre[NW];
+        int nq = 0, nm = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { qpre[w] = nq; nq += s_qn[w]; mpre[w] = nm; nm += s_qo[w]; }
+        for (int t = tid; t < nq; t += NT) {
+            int rec = t;  // the last wave whose first index is <= t (waves may queue none)
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                if (t >= qpre[k]) rec = k * rw + (t - qpre[k]);
+            queued(rec, true);
+        }
+        for (int t = tid; t < nm; t += NT) {
+            int rec = rw - 1 - t;
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                if (t >= mpre[k]) rec = k * rw + rw - 1 - (t - mpre[k]);
+            queued(rec, false);
+        }
+    } else {
+        const int nq = s_queue;
+        for (int t = tid; t < nq; t += NT) queued(t, false);
     }
 
     // ---- hand the leavers to their destination supercells' arrival lists

@@ -25,13 +25,15 @@ _SRC = os.path.join(_HERE, "pic_oracle.c")
 _lib = None
 
 
-def build() -> str:
-    """Compile the C oracle (IEEE FP64: no fast-math, no FMA contraction)."""
-    tmp = _SO + ".tmp"
+def build(src: str = _SRC, out: str = _SO) -> str:
+    """Compile the C oracle (IEEE FP64: no fast-math, no FMA contraction).
+    src / out name another copy of the source and its library (the tests
+    compile copies with planted mistakes to show that the pins catch them)."""
+    tmp = out + ".tmp"
     subprocess.check_call(["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _SO)
-    return _SO
+                           "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
 
 
 def lib():
@@ -42,6 +44,20 @@ def lib():
         _lib = C.CDLL(_SO)
         _declare(_lib)
     return _lib
+
+
+def load_library(path: str):
+    """A compiled copy of the oracle at `path`, declared like the default one."""
+    L = C.CDLL(path)
+    _declare(L)
+    return L
+
+
+def use_library(L):
+    """Make L the library every wrapper below calls; returns the previous one."""
+    global _lib
+    prev, _lib = lib(), L
+    return prev
 
 
 class Grid(C.Structure):

@@ -168,12 +168,16 @@ typedef struct pic_ctx pic_ctx;
 int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species, int n_species,
              pic_shape_t shape, const pic_alloc_t* alloc, void* hip_stream);
 
-/* Advance n >= 0 PIC cycles.  Each cycle: zero J; per mobile species and
- * supercell, stage E,B (+guards) in LDS, gather + Boris + move + Esirkepov
- * into an LDS current tile flushed once to J; migrate particles that left
- * their supercell; B half step, E full step with -J, B half step.
- * Asynchronous on the stream except for one small read of the device error
- * flags at the end (PIC_ERR_CAPACITY, PIC_ERR_CFL). */
+/* Advance n >= 0 PIC cycles.  Each cycle: zero J; per mobile species one
+ * particle-kernel launch in which each supercell first takes in the particles
+ * that arrived from its neighbours in the previous cycle (closing the holes
+ * they left), then stages E,B (+guards) in LDS, runs gather + Boris + move +
+ * Esirkepov into an LDS current tile flushed once to J, and hands the
+ * particles that left it to their destination's arrival list; then B half
+ * step, E full step with -J, B half step.  After the last cycle one migration
+ * pass takes in the last arrivals, so the frames are dense when the call
+ * returns.  Asynchronous on the stream except for one small read of the
+ * device error flags at the end (PIC_ERR_CAPACITY, PIC_ERR_CFL). */
 int pic_step(pic_ctx* ctx, int n);
 
 typedef struct {

@@ -54,16 +54,16 @@ enum Purpose {
 // Overloads for the templated PIC kernels (R = float or double).  1/sqrt and
 // 1/x are the hardware approximations in FP32 (the push stays within its
 // parity bound by a wide margin) and IEEE sqrt and division in FP64.
-__device__ inline float rfloor(float x) { return floorf(x); }
-__device__ inline double rfloor(double x) { return floor(x); }
-__device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
-__device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
-__device__ inline float rabs(float x) { return fabsf(x); }
-__device__ inline double rabs(double x) { return fabs(x); }
-__device__ inline float rmin(float a, float b) { return fminf(a, b); }
-__device__ inline double rmin(double a, double b) { return fmin(a, b); }
-__device__ inline float rmax(float a, float b) { return fmaxf(a, b); }
-__device__ inline double rmax(double a, double b) { return fmax(a, b); }
+__host__ __device__ inline float rfloor(float x) { return floorf(x); }
+__host__ __device__ inline double rfloor(double x) { return floor(x); }
+__host__ __device__ inline float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ inline double rfma(double a, double b, double c) { return fma(a, b, c); }
+__host__ __device__ inline float rabs(float x) { return fabsf(x); }
+__host__ __device__ inline double rabs(double x) { return fabs(x); }
+__host__ __device__ inline float rmin(float a, float b) { return fminf(a, b); }
+__host__ __device__ inline double rmin(double a, double b) { return fmin(a, b); }
+__host__ __device__ inline float rmax(float a, float b) { return fmaxf(a, b); }
+__host__ __device__ inline double rmax(double a, double b) { return fmax(a, b); }
 __device__ inline float rrsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rrsq(double x) { return 1.0 / sqrt(x); }
 __device__ inline float rrcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -79,7 +79,7 @@ __device__ inline double4 make4(double a, double b, double c, double d) { return
 // PCS (cubic B-spline): nodes f-1 .. f+2 with f = floor(x), d = x - f, e = 1 - d:
 //      e^3/6, 2/3 - d^2 (1 - d/2), 2/3 - e^2 (1 - e/2), d^3/6.
 template <int ORDER, class R>
-__device__ inline int shape_weights(R x, R* w)
+__host__ __device__ inline int shape_weights(R x, R* w)
 {
     static_assert(ORDER >= 0 && ORDER <= 3, "NGP, CIC, TSC or PCS");
     if constexpr (ORDER == 0) {

@@ -4,8 +4,12 @@
 // Golub & Welsch (Math. Comp. 23, 1969): the nodes are the eigenvalues of the
 // symmetric tridiagonal Jacobi matrix of the Laguerre recurrence (diagonal
 // 2k+1, off-diagonal k) and the weights the squared first components of its
-// normalised eigenvectors.  The eigenproblem is solved by implicit-shift QL
-// iterations that accumulate only the first row of the rotations.  Each node
+// normalised eigenvectors.  The eigenproblem is solved by the implicit-shift
+// QL algorithm for symmetric tridiagonal matrices (Bowdler, Martin, Reinsch &
+// Wilkinson, Numer. Math. 11, 1968; EISPACK tql1/tql2): Wilkinson shift from
+// the leading 2x2 block, a sweep of plane rotations that chases the bulge,
+// and a restart where an off-diagonal element underflows.  Only the first row
+// of the accumulated rotations is kept, which is all the weights need.  Each node
 // is then polished by Newton steps on L_n evaluated with the three-term
 // recurrence, and the weights are recomputed as x / ((n+1) L_{n+1}(x))^2,
 // which keeps full relative accuracy for the tiny weights of the large nodes.

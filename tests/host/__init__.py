@@ -1,0 +1,30 @@
+"""Host builds of product code for CPU tests (test infrastructure).
+
+`deposit_host.hip` drives the particle kernel's deposit arithmetic on the CPU;
+build() compiles it with hipcc (host code only runs; the device part is empty).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BUILD = os.path.join(HERE, "_build")
+SO = os.path.join(BUILD, "libdeposit_host.so")
+CSRC = os.path.join(os.path.dirname(os.path.dirname(HERE)), "paper_1606_02862_amd", "csrc")
+SOURCES = [os.path.join(HERE, "deposit_host.hip")] + [
+    os.path.join(CSRC, f) for f in ("pic_deposit.hpp", "pic_device.hpp", "pic_internal.hpp")]
+
+
+def build(force: bool = False) -> str:
+    """Compile libdeposit_host.so if it is missing or older than its sources."""
+    if not force and os.path.exists(SO):
+        t = os.path.getmtime(SO)
+        if all(os.path.getmtime(s) <= t for s in SOURCES):
+            return SO
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = SO + ".tmp"
+    subprocess.check_call(["hipcc", "-O2", "-std=c++17", "--offload-arch=gfx950", "-shared", "-fPIC",
+                           "-o", tmp, SOURCES[0]], stderr=subprocess.DEVNULL)
+    os.replace(tmp, SO)
+    return SO

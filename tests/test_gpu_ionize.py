@@ -80,8 +80,12 @@ def _shared_carbon_state(pic, cfg, warm=4):
 
 
 def test_ionize_exact_matches_oracle(P):
-    cfg = _carbon_cfg()
-    ncell = 16 * 16 * 8
+    # 32x16x16 cells, 32768 C2+ ions: this state fires about 80 events in the
+    # step (the oracle counts 84), enough to compare decisions, appended
+    # electrons and their ids on a real sample
+    box = (32, 16, 16)
+    cfg = _carbon_cfg(box)
+    ncell = box[0] * box[1] * box[2]
     n_e0, n_c0 = ncell * 8, ncell * 4
     with P.Pic(cfg) as pic:
         s0 = _shared_carbon_state(pic, cfg)
@@ -92,7 +96,7 @@ def test_ionize_exact_matches_oracle(P):
     fire_ref = d["fire"]
     _print("ionised gpu/ref", stats["ionized"], int(fire_ref.sum()), "active", stats["ions_active"])
     assert stats["ions_active"] == n_c0
-    assert fire_ref.sum() > 5  # the test state must actually ionise
+    assert fire_ref.sum() > 20  # the test state must actually ionise
     # decisions may differ only where r is within FP64 rounding of p
     zg = got.species[1].zstate
     zr = ref.species[1].zstate

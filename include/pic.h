@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 5
+#define PIC_ABI_VERSION 6
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
 #define PIC_LOTZ_SHELLS 3
@@ -98,8 +98,27 @@ typedef struct {
     uint64_t seed;      /* Philox key for every random draw */
     double n_ref_cm3;   /* physical density of n0 = 1, used only by ionisation */
     int32_t gather;     /* pic_gather_t (0: standard) */
-    int32_t reserved1;
+    int32_t options;    /* PIC_OPT_* bits (0: none) */
 } pic_grid_t;
+
+/* Options of pic_grid_t.options.
+ *
+ * PIC_OPT_DETERMINISTIC_J (FP32 only): every supercell's exact 64-bit
+ *   fixed-point current tile is added to a 64-bit fixed-point copy of J in
+ *   device memory with integer atomics (one scale for all species in a cycle,
+ *   2^30 over the largest bound of one particle's contribution), and J is
+ *   converted to FP32 once per cycle.  Integer sums do not depend on the order
+ *   of the additions, so the cycle's results are bit-reproducible: two runs
+ *   from the same state give identical particles and fields.  Without it the
+ *   overlapping tiles are added with FP32 atomics, whose order varies.  Costs
+ *   24 more bytes per cell and cycle of device traffic (the fixed-point copy
+ *   is zeroed and read back) and 24 bytes per cell of memory.
+ * PIC_OPT_CONTINUITY: pic_step keeps the FP64 charge density of the state
+ *   before its last cycle, so that pic_moments can report that cycle's
+ *   continuity residual (pic_moments_t.continuity_max).  Costs one charge
+ *   deposit and one extra migration pass per pic_step call. */
+#define PIC_OPT_DETERMINISTIC_J 1
+#define PIC_OPT_CONTINUITY 2
 
 /* One Lotz subshell of a charge state (Lotz 1968):
  *   sigma_j(E) = a q ln(E/p) / (E p) [1 - b e^{-c (E/p - 1)}]  for E >= p.
@@ -193,11 +212,44 @@ typedef struct {
     int64_t step;                        /* cycles taken since init */
     int32_t nonfinite;                   /* number of non-finite E, B entries */
     int32_t reserved;
+    /* Continuity residual of the last cycle of the last pic_step call,
+     *   max over nodes |div J + (rho^{n+1} - rho^n) / dt|,
+     * with div J the backward difference of J (the stencil of div E),
+     * rho^n the FP64 charge density at the nodes before that cycle and rho^{n+1}
+     * now; zero up to the rounding of J for the Esirkepov deposit.  -1 when the
+     * handle lacks PIC_OPT_CONTINUITY, no cycle ran yet, or particles, fields
+     * or charge states changed since (pic_set_*, pic_ionize). */
+    double continuity_max;
+    double j_max;                        /* max |J| over components and cells */
 } pic_moments_t;
 
 /* FP64 diagnostics (two-pass reductions on the GPU), synchronous.
  * Returns PIC_ERR_NONFINITE (after filling *out) if a field is not finite. */
 int pic_moments(pic_ctx* ctx, pic_moments_t* out);
+
+/* Run state beyond particles and fields, for checkpoint and resume.
+ *   step          cycles taken since init; keys the Philox draws of pic_ionize
+ *   seed          the Philox key of every draw (pic_grid_t.seed at init)
+ *   weight_bound  per species, the bound of |w| that sets the 64-bit
+ *                 fixed-point scale of the current tile, 2^30 over
+ *                 |q w_bound| max(dx,dy,dz) / (dV dt)
+ * A run checkpointed with pic_get_particles / pic_get_fields /
+ * pic_get_run_state and resumed on a handle created with the same grid and
+ * species, by pic_set_particles, pic_set_fields and then pic_set_run_state,
+ * continues exactly as the uninterrupted run (bit for bit with
+ * PIC_OPT_DETERMINISTIC_J).  set: PIC_ERR_ARG for step < 0, or for a bound
+ * that is not finite or lies below the largest |w| of the species' particles
+ * (as known to the handle: from init, pic_set_particles and the electrons
+ * pic_ionize adds).  The Gauss reference G0 is not part of it: the resumed
+ * handle records its own (pic_mark_reference). */
+typedef struct {
+    int64_t step;
+    uint64_t seed;
+    double weight_bound[PIC_MAX_SPECIES];
+} pic_run_state_t;
+
+int pic_get_run_state(pic_ctx* ctx, pic_run_state_t* out);
+int pic_set_run_state(pic_ctx* ctx, const pic_run_state_t* in);
 
 /* Particle transfer.  Host arrays of `count` entries; positions are global,
  * in cell units, inside [0, n_d).  zstate may be NULL for species without

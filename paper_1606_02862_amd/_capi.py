@@ -21,7 +21,7 @@ class GridT(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
                 ("b0", C.c_double * 3), ("rho_bg", C.c_double), ("seed", C.c_uint64), ("n_ref_cm3", C.c_double),
-                ("gather", C.c_int32), ("reserved1", C.c_int32)]
+                ("gather", C.c_int32), ("options", C.c_int32)]
 
 
 class LotzShellT(C.Structure):
@@ -51,7 +51,12 @@ class MomentsT(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_b", C.c_double), ("kinetic", C.c_double * PIC_MAX_SPECIES),
                 ("kinetic_total", C.c_double), ("charge_total", C.c_double), ("rho_max", C.c_double),
                 ("gauss_max", C.c_double), ("divb_max", C.c_double), ("count", C.c_int64 * PIC_MAX_SPECIES),
-                ("step", C.c_int64), ("nonfinite", C.c_int32), ("reserved", C.c_int32)]
+                ("step", C.c_int64), ("nonfinite", C.c_int32), ("reserved", C.c_int32),
+                ("continuity_max", C.c_double), ("j_max", C.c_double)]
+
+
+class RunStateT(C.Structure):
+    _fields_ = [("step", C.c_int64), ("seed", C.c_uint64), ("weight_bound", C.c_double * PIC_MAX_SPECIES)]
 
 
 class ParticlesView64T(C.Structure):
@@ -93,6 +98,7 @@ class MlpReportT(C.Structure):
 PIC_MLP_NPARAM = 4801
 PIC_MLP_SILU, PIC_MLP_RELU = 0, 1
 PIC_RATE_EXACT, PIC_RATE_MLP = 0, 1
+PIC_OPT_DETERMINISTIC_J, PIC_OPT_CONTINUITY = 1, 2
 
 _DP = C.POINTER(C.c_double)
 _FP = C.POINTER(C.c_float)
@@ -105,6 +111,8 @@ SIGNATURES = {
                            C.POINTER(AllocT), C.c_void_p]),
     "pic_step": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_moments": (C.c_int, [C.c_void_p, C.POINTER(MomentsT)]),
+    "pic_get_run_state": (C.c_int, [C.c_void_p, C.POINTER(RunStateT)]),
+    "pic_set_run_state": (C.c_int, [C.c_void_p, C.POINTER(RunStateT)]),
     "pic_particle_count": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
     "pic_get_particles": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ParticlesViewT)]),
     "pic_set_particles": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ParticlesViewT)]),

@@ -64,8 +64,8 @@ __global__ __launch_bounds__(BLOCK) void k_field_energy(GridViewT<R> g, double* 
 // scaled by scale[v], as a sum or (op bit v set) a maximum.
 struct Finalize {
     int nb, stride, nvals;
-    int dst[4];
-    double scale[4];
+    int dst[8];
+    double scale[8];
     unsigned max_mask;
 };
 
@@ -224,15 +224,20 @@ hipError_t launch_rho_deposit(const GridViewT<R>& g, const SpeciesViewT<R>& s, i
 
 // ---------------------------------------------------------------- Gauss
 // mode 0: store G = div E - rho as the reference; mode 1: reduce
-// max |G - G0|, max |rho|, sum rho dV and max |div B| (at cell centres).
+// max |G - G0|, max |rho|, sum rho dV, max |div B| (at cell centres), max |J|
+// and, with rho_prev, the continuity residual max |div J + (rho - rho_prev)/dt|
+// (div J with the backward differences of div E, at the nodes).
+constexpr int GAUSS_VALS = 6;
+
 template <class R>
 __global__ __launch_bounds__(BLOCK) void k_gauss(GridViewT<R> g, const double* rho, double* g0, double rho_bg, int mode,
-                                                 double* partial)
+                                                 const double* rho_prev, double* partial)
 {
     __shared__ double scratch[BLOCK / 64];
     const int N = g.nx * g.ny * g.nz;
     const double idx = 1.0 / (double)g.dx, idy = 1.0 / (double)g.dy, idz = 1.0 / (double)g.dz;
-    double gmax = 0.0, rmax = 0.0, rsum = 0.0, bmax = 0.0;
+    const double idt = 1.0 / (double)g.dt;
+    double gmax = 0.0, rmax = 0.0, rsum = 0.0, bmax = 0.0, cmax = 0.0, jmax = 0.0;
     for (int c = blockIdx.x * BLOCK + threadIdx.x; c < N; c += gridDim.x * BLOCK) {
         const int i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
         const int im = (i == 0) ? c + g.nx - 1 : c - 1;
@@ -256,6 +261,13 @@ __global__ __launch_bounds__(BLOCK) void k_gauss(GridViewT<R> g, const double* r
             rmax = fmax(rmax, fabs(r));
             rsum += r;
             bmax = fmax(bmax, fabs(divB));
+            jmax = fmax(jmax, fmax(fabs((double)g.J[c]), fmax(fabs((double)g.J[N + c]), fabs((double)g.J[2 * N + c]))));
+            if (rho_prev) {
+                const double divJ = ((double)g.J[c] - (double)g.J[im]) * idx +
+                                    ((double)g.J[N + c] - (double)g.J[N + jm]) * idy +
+                                    ((double)g.J[2 * N + c] - (double)g.J[2 * N + km]) * idz;
+                cmax = fmax(cmax, fabs(divJ + (rho[c] - rho_prev[c]) * idt));
+            }
         }
     }
     if (mode == 0) return;
@@ -263,28 +275,37 @@ __global__ __launch_bounds__(BLOCK) void k_gauss(GridViewT<R> g, const double* r
     rmax = block_reduce(rmax, true, scratch);
     rsum = block_reduce(rsum, false, scratch);
     bmax = block_reduce(bmax, true, scratch);
+    cmax = block_reduce(cmax, true, scratch);
+    jmax = block_reduce(jmax, true, scratch);
     if (threadIdx.x == 0) {
-        partial[4 * blockIdx.x + 0] = gmax;
-        partial[4 * blockIdx.x + 1] = rmax;
-        partial[4 * blockIdx.x + 2] = rsum;
-        partial[4 * blockIdx.x + 3] = bmax;
+        double* p = partial + GAUSS_VALS * blockIdx.x;
+        p[0] = gmax;
+        p[1] = rmax;
+        p[2] = rsum;
+        p[3] = bmax;
+        p[4] = cmax;  // 0 without rho_prev
+        p[5] = jmax;
     }
 }
 
 template <class R>
-hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st)
+hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, bool cont, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gauss<R>, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.rho, d.g0, rho_bg, mode, d.partial);
+    if (mode != 0 && d.npartial < GAUSS_VALS * RED_BLOCKS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gauss<R>, dim3(RED_BLOCKS), dim3(BLOCK), 0, st, g, d.rho, d.g0, rho_bg, mode,
+                       cont ? (const double*)d.rho_prev : nullptr, d.partial);
     if (mode == 0) return hipGetLastError();
     Finalize f{};
     f.nb = RED_BLOCKS;
-    f.stride = 4;
-    f.nvals = 4;
+    f.stride = GAUSS_VALS;
+    f.nvals = GAUSS_VALS;
     f.dst[0] = D_GAUSS; f.scale[0] = 1.0;
     f.dst[1] = D_RHOMAX; f.scale[1] = 1.0;
     f.dst[2] = D_CHARGE; f.scale[2] = (double)g.dx * g.dy * g.dz;
     f.dst[3] = D_DIVB; f.scale[3] = 1.0;
-    f.max_mask = 0b1011;
+    f.dst[4] = D_CONT; f.scale[4] = 1.0;
+    f.dst[5] = D_JMAX; f.scale[5] = 1.0;
+    f.max_mask = 0b111011;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, st, d.partial, f, d.result);
     return hipGetLastError();
 }
@@ -295,7 +316,7 @@ hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_
                                           hipStream_t);                                                       \
     template hipError_t launch_rho_deposit<R>(const GridViewT<R>&, const SpeciesViewT<R>&, int, double*,       \
                                               hipStream_t);                                                   \
-    template hipError_t launch_gauss<R>(const GridViewT<R>&, const DiagBuffers&, double, int, hipStream_t);
+    template hipError_t launch_gauss<R>(const GridViewT<R>&, const DiagBuffers&, double, int, bool, hipStream_t);
 PIC_DIAG_INSTANCES(float)
 PIC_DIAG_INSTANCES(double)
 #undef PIC_DIAG_INSTANCES

@@ -1,7 +1,8 @@
 // Yee FDTD updates on the periodic staggered grid (Yee 1966), one lane per
 // cell, x fastest so every component row is read and written coalesced:
 //   B -= coef * curl E   (forward differences of E, at the B locations)
-//   E += coef * (curl B - J)   (backward differences of B, at the E locations)
+//   E += coef * (curl B - J)   (backward differences of B, at the E locations;
+//                               J converted from its fixed-point sums first when kept so)
 // The PIC cycle applies B(dt/2), E(dt), B(dt/2).
 #include "pic_device.hpp"
 
@@ -46,9 +47,22 @@ __global__ __launch_bounds__(BLOCK) void k_yee_e(GridViewT<R> g, R cx, R cy, R c
     const R curl_x = cy * (bz - Bz[jm]) - cz * (by - By[km]);
     const R curl_y = cz * (bx - Bx[km]) - cx * (bz - Bz[im]);
     const R curl_z = cx * (by - By[im]) - cy * (bx - Bx[jm]);
-    g.E[c] += curl_x - coef * g.J[c];
-    g.E[N + c] += curl_y - coef * g.J[N + c];
-    g.E[2 * N + c] += curl_z - coef * g.J[2 * N + c];
+    R jx, jy, jz;
+    if (g.J64) {  // PIC_OPT_DETERMINISTIC_J: J from its fixed-point sums (kept in g.J too)
+        jx = (R)((double)(long long)g.J64[c] * g.jinv64);
+        jy = (R)((double)(long long)g.J64[N + c] * g.jinv64);
+        jz = (R)((double)(long long)g.J64[2 * N + c] * g.jinv64);
+        g.J[c] = jx;
+        g.J[N + c] = jy;
+        g.J[2 * N + c] = jz;
+    } else {
+        jx = g.J[c];
+        jy = g.J[N + c];
+        jz = g.J[2 * N + c];
+    }
+    g.E[c] += curl_x - coef * jx;
+    g.E[N + c] += curl_y - coef * jy;
+    g.E[2 * N + c] += curl_z - coef * jz;
 }
 
 // coef / dx etc. are rounded to R once on the host side of the launch

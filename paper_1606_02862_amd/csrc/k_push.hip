@@ -160,12 +160,27 @@ __device__ inline void st_part(E* base, unsigned byte_off, E v)
     else at(base, byte_off) = v;
 }
 
+// Add one node of a supercell's fixed-point current tile to global J: as an
+// FP32 atomic, or (PIC_OPT_DETERMINISTIC_J) rescaled to the cycle's common
+// scale (jratio <= 1, rounded to nearest) and added to the 64-bit fixed-point
+// J, whose integer sums do not depend on the order of the tiles.
+__device__ inline void flush_node(const GridView& g, int i, long long iv, float jinv, double jratio)
+{
+    if (iv == 0) return;
+    if (g.J64) {
+        const long long v = jratio == 1.0 ? iv : __double2ll_rn((double)iv * jratio);
+        if (v != 0) atomicAdd(&g.J64[i], (unsigned long long)v);
+    } else {
+        unsafeAtomicAdd(&g.J[i], (float)((double)iv * (double)jinv));
+    }
+}
+
 // Waves per SIMD the register budget is fitted to: 4 in FP32, 2 in FP64.
 template <class R> constexpr int push_waves() { return std::is_same<R, float>::value ? 4 : 2; }
 
 template <int ORDER, bool HAS_Z, bool GAL, int NT, class R>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(push_waves<R>())))
-void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int wpar)
+void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, int apar, int wpar)
 {
     using T = Tile<ORDER, R>;
     using A = JAcc<R>;
@@ -514,7 +529,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
                 if (tz >= PcsTile::jz(c)) continue;
                 if constexpr (std::is_same<R, float>::value) {
                     const long long iv = (long long)tJ[PcsTile::joff(c) + t];
-                    if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+                    flush_node(g, c * N + gi, iv, jinv, jratio);
                 } else {
                     const double v = tJ[PcsTile::joff(c) + t];
                     if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
@@ -533,7 +548,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
             for (int c = 0; c < 3; ++c) {
                 if constexpr (std::is_same<R, float>::value) {
                     const long long iv = (long long)tJ[c * T::JN + t];
-                    if (iv != 0) unsafeAtomicAdd(&g.J[c * N + gi], (float)((double)iv * (double)jinv));
+                    flush_node(g, c * N + gi, iv, jinv, jratio);
                 } else {
                     const double v = tJ[c * T::JN + t];
                     if (v != 0.0) unsafeAtomicAdd(&g.J[c * N + gi], v);
@@ -549,43 +564,49 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, int apar, int w
 }
 
 template <int ORDER, int NT, class R>
-static void launch_push_order(const GridViewT<R>& g, const SpeciesViewT<R>& s, bool gal, R jscale, R jinv, int apar,
-                              int wpar, hipStream_t st)
+static void launch_push_order(const GridViewT<R>& g, const SpeciesViewT<R>& s, bool gal, R jscale, R jinv,
+                              double jratio, int apar, int wpar, hipStream_t st)
 {
     const dim3 grid(g.nsc), block(NT);
     const bool hz = s.zs != nullptr;
     if (gal) {
-        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<ORDER, false, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, jratio, apar, wpar);
+        else hipLaunchKernelGGL((k_push<ORDER, false, true, NT, R>), grid, block, 0, st, g, s, jscale, jinv, jratio, apar, wpar);
     } else {
-        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
-        else hipLaunchKernelGGL((k_push<ORDER, false, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, apar, wpar);
+        if (hz) hipLaunchKernelGGL((k_push<ORDER, true, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, jratio, apar, wpar);
+        else hipLaunchKernelGGL((k_push<ORDER, false, false, NT, R>), grid, block, 0, st, g, s, jscale, jinv, jratio, apar, wpar);
     }
 }
 
 template <class R>
 hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, bool galerkin, double vmax,
-                       int apar, int wpar, hipStream_t st)
+                       float jscale_g, int apar, int wpar, hipStream_t st)
 {
     // the deposit queue holds a full supercell, split evenly over the waves of a workgroup
     const int nt = order == 1 ? 256 : 512;
     if ((s.cap + nt - 1) / nt * nt > g.qcap || g.qcap % (nt / 64) != 0) return hipErrorInvalidValue;
     if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
     R jscale = R(1), jinv = R(1);
+    double jratio = 1.0;
     if constexpr (std::is_same<R, float>::value) {
         // fixed-point scale: one contribution is at most vmax in magnitude -> |int| <= 2^30
-        const float vf = (float)vmax;
-        jscale = vf > 0.0f ? 1073741824.0f / vf : 1.0f;
+        jscale = fixed_scale(vmax);
         jinv = 1.0f / jscale;
+        // the common scale of the deterministic J is never finer than the species' own
+        if (g.J64) {
+            if (!(jscale_g > 0.0f) || jscale_g > jscale) return hipErrorInvalidValue;
+            jratio = (double)jscale_g / (double)jscale;
+        }
     }
-    if (order == 1) launch_push_order<1, 256>(g, s, galerkin, jscale, jinv, apar, wpar, st);
-    else if (order == 2) launch_push_order<2, 512>(g, s, galerkin, jscale, jinv, apar, wpar, st);
-    else launch_push_order<3, 512>(g, s, galerkin, jscale, jinv, apar, wpar, st);
+    if (order == 1) launch_push_order<1, 256>(g, s, galerkin, jscale, jinv, jratio, apar, wpar, st);
+    else if (order == 2) launch_push_order<2, 512>(g, s, galerkin, jscale, jinv, jratio, apar, wpar, st);
+    else launch_push_order<3, 512>(g, s, galerkin, jscale, jinv, jratio, apar, wpar, st);
     return hipGetLastError();
 }
 
-template hipError_t launch_push<float>(const GridView&, const SpeciesView&, int, bool, double, int, int, hipStream_t);
-template hipError_t launch_push<double>(const GridView64&, const SpeciesView64&, int, bool, double, int, int,
+template hipError_t launch_push<float>(const GridView&, const SpeciesView&, int, bool, double, float, int, int,
+                                       hipStream_t);
+template hipError_t launch_push<double>(const GridView64&, const SpeciesView64&, int, bool, double, float, int, int,
                                         hipStream_t);
 
 }  // namespace pic

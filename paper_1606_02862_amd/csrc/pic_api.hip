@@ -32,6 +32,7 @@ struct pic_ctx {
     std::vector<void*> owned;
     int32_t* flags_host = nullptr;  // pinned
     int64_t step = 0;
+    bool rho_prev_valid = false;    // diag.rho_prev holds rho before the last cycle (PIC_OPT_CONTINUITY)
     std::string err;
     // timing
     bool timing = false;
@@ -154,6 +155,10 @@ int validate(const pic_grid_t* g, const pic_species_t* sp, int n, pic_shape_t sh
         return fail(nullptr, PIC_ERR_ARG, "unknown precision %d", (int)g->precision);
     if (g->gather != PIC_GATHER_STANDARD && g->gather != PIC_GATHER_GALERKIN)
         return fail(nullptr, PIC_ERR_ARG, "unknown gather %d", (int)g->gather);
+    if (g->options & ~(PIC_OPT_DETERMINISTIC_J | PIC_OPT_CONTINUITY))
+        return fail(nullptr, PIC_ERR_ARG, "unknown options 0x%x", (unsigned)g->options);
+    if ((g->options & PIC_OPT_DETERMINISTIC_J) && g->precision != PIC_PRECISION_FP32)
+        return fail(nullptr, PIC_ERR_ARG, "PIC_OPT_DETERMINISTIC_J needs FP32 (the FP64 tile sums are floating point)");
     if (n < 1 || n > PIC_MAX_SPECIES) return fail(nullptr, PIC_ERR_ARG, "n_species must be in 1..%d", PIC_MAX_SPECIES);
     double ids = 0.0;
     for (int s = 0; s < n; ++s) {
@@ -386,7 +391,7 @@ int mark_reference_t(pic_ctx* c)
     HIPCHK(c, launch_zero_f64(c->diag.rho, N, c->stream));
     for (int s = 0; s < c->nsp; ++s)
         HIPCHK(c, launch_rho_deposit<R>(gview<R>(c), sview<R>(c, s), c->order, c->diag.rho, c->stream));
-    HIPCHK(c, launch_gauss<R>(gview<R>(c), c->diag, c->grid.rho_bg, 0, c->stream));
+    HIPCHK(c, launch_gauss<R>(gview<R>(c), c->diag, c->grid.rho_bg, 0, false, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
@@ -552,6 +557,8 @@ int set_particles_t(pic_ctx* c, int s, const V* v)
     HIPCHK(c, hipMemcpyAsync(sv.count, cnt.data(), (size_t)g.nsc * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->sp[s].wmax = wmax;
+    c->sp[s].wheld = wmax;
+    c->rho_prev_valid = false;
     return PIC_OK;
 }
 
@@ -604,6 +611,7 @@ int set_fields_t(pic_ctx* c, const T* E, const T* B, const T* J)
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
     }
+    c->rho_prev_valid = false;
     return PIC_OK;
 }
 
@@ -621,13 +629,24 @@ int step_t(pic_ctx* c, int n)
             if (!e0 || !e1 || !e2 || !e3) return fail(c, PIC_ERR_HIP, "event creation failed");
             HIPCHK(c, hipEventRecord(e0, c->stream));
         }
-        HIPCHK(c, launch_zero_r(g.J, 3 * N, c->stream));
+        // the cycle's common fixed-point scale of the deterministic J: that of the largest bound
+        float jscale_g = 0.0f;
+        if (g.J64) {
+            double vg = 0.0;
+            for (int s = 0; s < c->nsp; ++s)
+                if (c->sp[s].desc.mobile) vg = std::max(vg, push_vmax(c, s));
+            jscale_g = fixed_scale(vg);
+            g.jinv64 = 1.0 / (double)jscale_g;
+            HIPCHK(c, launch_zero_f64(reinterpret_cast<double*>(g.J64), 3 * N, c->stream));  // all-zero bits
+        } else {
+            HIPCHK(c, launch_zero_r(g.J, 3 * N, c->stream));
+        }
         // step `it` writes its leavers to parity it & 1 and absorbs the previous step's
         const int wpar = it & 1, apar = it > 0 ? ((it - 1) & 1) : -1;
         for (int s = 0; s < c->nsp; ++s) {
             if (!c->sp[s].desc.mobile) continue;
             HIPCHK(c, launch_push<R>(g, sview<R>(c, s), c->order, c->grid.gather == PIC_GATHER_GALERKIN,
-                                     push_vmax(c, s), apar, wpar, c->stream));
+                                     push_vmax(c, s), jscale_g, apar, wpar, c->stream));
             c->pending_launches += c->timing ? 1 : 0;
         }
         if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -658,7 +677,18 @@ int moments_t(pic_ctx* c)
     HIPCHK(c, launch_zero_f64(c->diag.rho, N, c->stream));
     for (int s = 0; s < c->nsp; ++s)
         HIPCHK(c, launch_rho_deposit<R>(g, sview<R>(c, s), c->order, c->diag.rho, c->stream));
-    HIPCHK(c, launch_gauss<R>(g, c->diag, c->grid.rho_bg, 1, c->stream));
+    HIPCHK(c, launch_gauss<R>(g, c->diag, c->grid.rho_bg, 1, c->rho_prev_valid, c->stream));
+    return PIC_OK;
+}
+
+// rho before the next cycle, for the continuity residual of that cycle
+template <class R>
+int keep_rho_t(pic_ctx* c)
+{
+    const int64_t N = (int64_t)c->grid.nx * c->grid.ny * c->grid.nz;
+    HIPCHK(c, launch_zero_f64(c->diag.rho_prev, N, c->stream));
+    for (int s = 0; s < c->nsp; ++s)
+        HIPCHK(c, launch_rho_deposit<R>(gview<R>(c), sview<R>(c, s), c->order, c->diag.rho_prev, c->stream));
     return PIC_OK;
 }
 
@@ -732,11 +762,17 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         c->err = "device allocation of fields failed";
         return bail(PIC_ERR_OOM);
     }
-    c->diag.npartial = std::max(4 * 1024, g.nsc);
+    c->diag.npartial = std::max(8 * 1024, g.nsc);
     if (!(c->diag.rho = (double*)dev_alloc(c, N * 8)) || !(c->diag.g0 = (double*)dev_alloc(c, N * 8)) ||
         !(c->diag.partial = (double*)dev_alloc(c, (size_t)c->diag.npartial * 8)) ||
-        !(c->diag.result = (double*)dev_alloc(c, D_NSLOTS * 8))) {
+        !(c->diag.result = (double*)dev_alloc(c, D_NSLOTS * 8)) ||
+        ((grid->options & PIC_OPT_CONTINUITY) && !(c->diag.rho_prev = (double*)dev_alloc(c, N * 8)))) {
         c->err = "device allocation of diagnostics failed";
+        return bail(PIC_ERR_OOM);
+    }
+    if ((grid->options & PIC_OPT_DETERMINISTIC_J) &&
+        !(g.J64 = (unsigned long long*)dev_alloc(c, 3 * N * 8))) {
+        c->err = "device allocation of the fixed-point current failed";
         return bail(PIC_ERR_OOM);
     }
     const bool zero_failed =
@@ -744,7 +780,8 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
                    launch_zero_f64(g64.J, 3 * N, c->stream))
                 : (launch_zero_f32(g.E, 3 * N, c->stream) || launch_zero_f32(g.B, 3 * N, c->stream) ||
                    launch_zero_f32(g.J, 3 * N, c->stream));
-    if (zero_failed || launch_zero_i32(g.flags, 16, c->stream) || launch_zero_f64(c->diag.result, D_NSLOTS, c->stream)) {
+    if (zero_failed || launch_zero_i32(g.flags, 16, c->stream) || launch_zero_f64(c->diag.result, D_NSLOTS, c->stream) ||
+        (g.J64 && launch_zero_f64(reinterpret_cast<double*>(g.J64), 3 * N, c->stream))) {
         c->err = "field initialisation launch failed";
         return bail(PIC_ERR_HIP);
     }
@@ -758,6 +795,7 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         S.n_init = N * species[s].ppc;
         S.weight = species[s].ppc > 0 ? species[s].density * dV / species[s].ppc : 0.0;
         S.wmax = S.weight;
+        S.wheld = S.weight;
         off += S.n_init;
     }
     for (int s = 0; s < n_species; ++s) {
@@ -818,7 +856,16 @@ int pic_step(pic_ctx* c, int n)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (n < 0) return fail(c, PIC_ERR_ARG, "n must be >= 0");
-    const int rc0 = c->fp64 ? step_t<double>(c, n) : step_t<float>(c, n);
+    int rc0 = PIC_OK;
+    if ((c->grid.options & PIC_OPT_CONTINUITY) && n > 0) {
+        // the cycles but the last (frames dense again after them), rho, the last cycle
+        if (n > 1) rc0 = c->fp64 ? step_t<double>(c, n - 1) : step_t<float>(c, n - 1);
+        if (!rc0) rc0 = c->fp64 ? keep_rho_t<double>(c) : keep_rho_t<float>(c);
+        if (!rc0) rc0 = c->fp64 ? step_t<double>(c, 1) : step_t<float>(c, 1);
+        c->rho_prev_valid = rc0 == PIC_OK;
+    } else {
+        rc0 = c->fp64 ? step_t<double>(c, n) : step_t<float>(c, n);
+    }
     if (rc0) return rc0;
     if (c->timing) {
         // particles processed: counts before the step are what each push launch read
@@ -880,7 +927,35 @@ int pic_moments(pic_ctx* c, pic_moments_t* out)
     out->divb_max = r[D_DIVB];
     out->step = c->step;
     out->nonfinite = (int32_t)r[D_NONFINITE];
+    out->continuity_max = c->rho_prev_valid ? r[D_CONT] : -1.0;
+    out->j_max = r[D_JMAX];
     if (out->nonfinite) return fail(c, PIC_ERR_NONFINITE, "%d non-finite field entries", out->nonfinite);
+    return PIC_OK;
+}
+
+int pic_get_run_state(pic_ctx* c, pic_run_state_t* out)
+{
+    if (!c || !out) return fail(c, PIC_ERR_ARG, "ctx and out must not be NULL");
+    std::memset(out, 0, sizeof *out);
+    out->step = c->step;
+    out->seed = c->grid.seed;
+    for (int s = 0; s < c->nsp; ++s) out->weight_bound[s] = c->sp[s].wmax;
+    return PIC_OK;
+}
+
+int pic_set_run_state(pic_ctx* c, const pic_run_state_t* in)
+{
+    if (!c || !in) return fail(c, PIC_ERR_ARG, "ctx and in must not be NULL");
+    if (in->step < 0) return fail(c, PIC_ERR_ARG, "step must be >= 0");
+    for (int s = 0; s < c->nsp; ++s) {
+        const double b = in->weight_bound[s];
+        if (!std::isfinite(b) || b < c->sp[s].wheld)
+            return fail(c, PIC_ERR_ARG, "species %d: weight bound %g below the largest held |w| %g", s, b,
+                        c->sp[s].wheld);
+    }
+    c->step = in->step;
+    c->grid.seed = in->seed;
+    for (int s = 0; s < c->nsp; ++s) c->sp[s].wmax = in->weight_bound[s];
     return PIC_OK;
 }
 
@@ -964,6 +1039,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
             }
         }
     if (!nion) return fail(c, PIC_ERR_STATE, "no ionising species (z_max > 0 with ionize_into >= 0)");
+    c->rho_prev_valid = false;
     pic_ionize_stats_t st{};
     int64_t n0 = 0;
     for (int s = 0; s < c->nsp; ++s) n0 += c->sp[s].n_init;
@@ -1021,6 +1097,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         std::vector<int32_t> cc;
         st.electrons = host_count(c, e, cc);
         c->sp[e].wmax = std::max(c->sp[e].wmax, c->sp[s].wmax);  // born electrons carry ion weights
+        c->sp[e].wheld = std::max(c->sp[e].wheld, c->sp[s].wheld);
     }
     st.rate_ms = rate_ms;
     st.total_ms = total_ms;

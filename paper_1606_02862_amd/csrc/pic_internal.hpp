@@ -43,6 +43,11 @@ struct GridViewT {
     int32_t* flags;
     typename Vec4<R>::type* qbuf;  // deposit queue: nsc * qcap records of 2 (x0,y0,z0,qw | x1,y1,z1,-)
     int qcap;              // queue slots per supercell (>= every species' frame capacity; a multiple of 512)
+    // PIC_OPT_DETERMINISTIC_J (FP32): 3 * N int64 fixed-point current at the
+    // cycle's common scale, which the E update converts (times jinv64) into J;
+    // nullptr otherwise
+    unsigned long long* J64;
+    double jinv64;
 };
 
 template <class R>
@@ -83,7 +88,8 @@ struct Species {
     int64_t n_init;        // particles at t = 0
     int64_t id_offset;     // first id at t = 0
     double weight;
-    double wmax;           // largest |w| the species may hold (fixed-point current scale)
+    double wmax;           // bound of |w| that sets the fixed-point current scale (>= wheld)
+    double wheld;          // largest |w| known to be held (init, set, ionisation electrons)
 };
 
 // Map a workgroup index to a supercell so that the 8 XCDs (which receive
@@ -116,9 +122,17 @@ inline hipError_t launch_zero_r(double* p, int64_t n, hipStream_t st) { return l
 // apar: parity of the arrivals to absorb first (-1: none); wpar: parity the
 // leavers of this step are written to
 // galerkin: the reduced-order gather along staggered axes (PIC_GATHER_GALERKIN)
+// jscale_g: with g.J64, the cycle's common fixed-point scale (2^30 over the
+// largest vmax of the cycle's species); each tile is rescaled to it at the flush
 template <class R>
 hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, bool galerkin, double vmax,
-                       int apar, int wpar, hipStream_t st);
+                       float jscale_g, int apar, int wpar, hipStream_t st);
+// Fixed-point scale of a current tile: 2^30 over the bound vmax of one contribution.
+inline float fixed_scale(double vmax)
+{
+    const float vf = (float)vmax;
+    return vf > 0.0f ? 1073741824.0f / vf : 1.0f;
+}
 template <class R>
 hipError_t launch_migrate(const GridViewT<R>& g, const SpeciesViewT<R>& s, int par, hipStream_t st);
 template <class R>
@@ -132,6 +146,7 @@ struct DiagBuffers {
     double* g0;        // N, Gauss reference
     double* partial;   // scratch for block partial sums / maxima
     int npartial;
+    double* rho_prev;  // N, rho before the last cycle (PIC_OPT_CONTINUITY), or nullptr
     double* result;    // small device result vector
 };
 template <class R>
@@ -142,13 +157,16 @@ hipError_t launch_kinetic(const GridViewT<R>& g, const SpeciesViewT<R>& s, const
 template <class R>
 hipError_t launch_rho_deposit(const GridViewT<R>& g, const SpeciesViewT<R>& s, int order, double* rho,
                               hipStream_t st);
+// mode 0: record G0; mode 1: the reductions, plus the continuity residual
+// against d.rho_prev when cont is set
 template <class R>
-hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, hipStream_t st);
+hipError_t launch_gauss(const GridViewT<R>& g, const DiagBuffers& d, double rho_bg, int mode, bool cont, hipStream_t st);
 
 // Result vector layout of the diagnostics.
 enum DiagSlot {
     D_WE = 0, D_WB = 1, D_NONFINITE = 2, D_CHARGE = 3, D_RHOMAX = 4, D_GAUSS = 5, D_DIVB = 6,
     D_KIN0 = 8,  // + species index
+    D_CONT = 12, D_JMAX = 13,
     D_NSLOTS = 16
 };
 

@@ -45,6 +45,8 @@ def grid_struct(cfg: dict) -> A.GridT:
     g.n_ref_cm3 = gc.get("n_ref_cm3", 1e21)
     g.precision = _PRECISION[gc.get("precision", "fp32")]
     g.gather = {"standard": 0, "galerkin": 1}[gc.get("gather", "standard")]
+    g.options = ((A.PIC_OPT_DETERMINISTIC_J if gc.get("deterministic_j") else 0) |
+                 (A.PIC_OPT_CONTINUITY if gc.get("continuity") else 0))
     return g
 
 
@@ -107,7 +109,7 @@ class Pic:
     """One simulation on one GPU.  cfg is a workload dictionary (see
     workloads.py).  stream: a torch.cuda.Stream (default: the current one)."""
 
-    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, torch_alloc: bool = True):
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, torch_alloc: bool = True, allocator=None):
         import torch
         self.lib = A.load()
         self.cfg = cfg
@@ -118,7 +120,8 @@ class Pic:
         self.shape = cfg["grid"]["nx"], cfg["grid"]["ny"], cfg["grid"]["nz"]
         self.fp64 = cfg["grid"].get("precision", "fp32") == "fp64"
         self._rt = np.float64 if self.fp64 else np.float32  # host type of momenta, weights and fields
-        self._alloc = TorchAllocator(self.device) if torch_alloc else None
+        # allocator: an object with .struct (an AllocT), e.g. a TorchAllocator
+        self._alloc = allocator if allocator is not None else (TorchAllocator(self.device) if torch_alloc else None)
         self._g = grid_struct(cfg)
         self._s = species_structs(cfg)
         h = C.c_void_p()
@@ -155,9 +158,22 @@ class Pic:
         rc = self.lib.pic_moments(self.h, C.byref(m))
         d = dict(w_e=m.w_e, w_b=m.w_b, kinetic=list(m.kinetic)[: self.nsp], kinetic_total=m.kinetic_total,
                  charge_total=m.charge_total, rho_max=m.rho_max, gauss_max=m.gauss_max, divb_max=m.divb_max,
-                 count=list(m.count)[: self.nsp], step=m.step, nonfinite=m.nonfinite)
+                 count=list(m.count)[: self.nsp], step=m.step, nonfinite=m.nonfinite,
+                 continuity_max=m.continuity_max, j_max=m.j_max)
         A.check(rc, self.h)
         return d
+
+    def get_run_state(self) -> dict:
+        r = A.RunStateT()
+        A.check(self.lib.pic_get_run_state(self.h, C.byref(r)), self.h)
+        return dict(step=r.step, seed=r.seed, weight_bound=list(r.weight_bound)[: self.nsp])
+
+    def set_run_state(self, st: dict):
+        r = A.RunStateT()
+        r.step, r.seed = st["step"], st["seed"]
+        for i, b in enumerate(st["weight_bound"]):
+            r.weight_bound[i] = b
+        A.check(self.lib.pic_set_run_state(self.h, C.byref(r)), self.h)
 
     def mark_reference(self):
         A.check(self.lib.pic_mark_reference(self.h), self.h)

@@ -67,6 +67,8 @@ def _init(A, cfg, shape=None, nsp=None, mutate=None):
     ("ionize_into without charge states", lambda g, s: setattr(s[0], "ionize_into", 0), "ionize_into"),
     ("cap below ppc", lambda g, s: setattr(s[0], "cap_ppc", 3), "cap_ppc"),
     ("unknown gather", lambda g, s: setattr(g, "gather", 2), "gather"),
+    ("unknown option", lambda g, s: setattr(g, "options", 4), "options"),
+    ("deterministic J in FP64", lambda g, s: (setattr(g, "options", 1), setattr(g, "precision", 1)), "FP32"),
 ])
 def test_init_rejects_bad_arguments(A, what, mutate, needle):
     rc, h, msg = _init(A, workloads.config(0), mutate=mutate)
@@ -119,9 +121,12 @@ def test_null_handles(A):
     lib = A.load()
     assert lib.pic_step(None, 1) == A.PIC_ERR_ARG
     assert lib.pic_destroy(None) == A.PIC_OK
-    assert lib.pic_abi_version() == 5
+    assert lib.pic_abi_version() == 6
     m = A.MomentsT()
     assert lib.pic_moments(None, C.byref(m)) == A.PIC_ERR_ARG
+    r = A.RunStateT()
+    assert lib.pic_get_run_state(None, C.byref(r)) == A.PIC_ERR_ARG
+    assert lib.pic_set_run_state(None, C.byref(r)) == A.PIC_ERR_ARG
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
@@ -172,7 +177,7 @@ def test_struct_layouts_match_the_header(A, tmp_path):
              "pic_alloc_t": A.AllocT, "pic_moments_t": A.MomentsT, "pic_particles_view_t": A.ParticlesViewT,
              "pic_particles64_view_t": A.ParticlesView64T, "pic_timing_t": A.TimingT,
              "pic_ionize_stats_t": A.IonizeStatsT, "pic_mlp_train_cfg_t": A.MlpTrainCfgT,
-             "pic_mlp_report_t": A.MlpReportT}
+             "pic_mlp_report_t": A.MlpReportT, "pic_run_state_t": A.RunStateT}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pic.h"', "int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

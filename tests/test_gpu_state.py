@@ -1,0 +1,250 @@
+"""Run state through the C ABI on the GPU: the continuity residual that
+pic_moments reports, the order-independent (deterministic) current flush,
+checkpoint and resume, and allocation failure.
+
+Bars: the continuity residual max|div J + (rho^{n+1} - rho^n)/dt| of the
+Esirkepov deposit is rounding only (<= 2e-5 max|J| / min(dx, dy, dz) in FP32,
+<= 1e-11 in FP64) and equals the one recomputed from the pulled states with the
+oracle's charge density; with PIC_OPT_DETERMINISTIC_J two runs from one state
+are bit-identical and still meet the one-step parity bars; a run split by
+get/set of particles, fields and run state matches the uninterrupted run bit
+for bit, ionisation included; every allocation failure of pic_init returns
+PIC_ERR_OOM and hands back every block it took.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_02862_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# continuity residual
+
+@pytest.mark.parametrize("idx,box,shape,precision", [
+    (1, (16, 16, 8), "cic", "fp32"),     # shear layer: many cell and supercell crossings
+    (2, (16, 16, 8), "tsc", "fp32"),     # electrons + protons in B0
+    (0, (16, 16, 16), "pcs", "fp32"),
+    (2, (16, 16, 8), "tsc", "fp64"),
+])
+def test_continuity_residual(P, idx, box, shape, precision):
+    cfg = workloads.config(idx, nx=box[0], ny=box[1], nz=box[2], shape=shape, precision=precision,
+                           continuity=True)
+    _print("continuity", idx, box, shape, precision)
+    like = oracle.init_state(cfg)
+    with P.Pic(cfg) as pic:
+        assert pic.moments()["continuity_max"] == -1.0   # no cycle yet
+        pic.step(4)
+        m4 = pic.moments()
+        prev = parity.pull_state(pic, like)
+        pic.step(1)
+        m = pic.moments()
+        now = parity.pull_state(pic, like)
+        E, B, J = pic.get_fields()
+        pic.set_fields(E=E)                                # any change of state voids it
+        assert pic.moments()["continuity_max"] == -1.0
+    g = now.grid
+    res = oracle.div_nodes(g, now.J) + (oracle.rho(now) - oracle.rho(prev)) / cfg["grid"]["dt"]
+    ref = float(np.abs(res).max())
+    scale = m["j_max"] / min(g.dx, g.dy, g.dz)
+    _print("residual gpu", m["continuity_max"], "recomputed", ref, "max|div J| scale", scale)
+    assert m4["continuity_max"] >= 0.0
+    assert m["j_max"] == pytest.approx(float(np.abs(now.J).max()), rel=1e-12)
+    assert m["continuity_max"] <= (2e-5 if precision == "fp32" else 1e-11) * scale
+    # the same residual from the pulled states and the oracle's charge density
+    assert abs(m["continuity_max"] - ref) <= 1e-9 * scale
+
+
+def test_continuity_residual_unavailable_without_option(P):
+    cfg = workloads.reduced(0, 16, 16, 16)
+    with P.Pic(cfg) as pic:
+        pic.step(2)
+        assert pic.moments()["continuity_max"] == -1.0
+
+
+# ---------------------------------------------------------------------------
+# deterministic current flush
+
+def _all_state(pic, nsp):
+    E, B, J = pic.get_fields()
+    parts = [pic.get_particles(s) for s in range(nsp)]
+    return E, B, J, parts
+
+
+def _assert_bitwise(a, b):
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+    for pa, pb in zip(a[3], b[3]):
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+
+
+@pytest.mark.parametrize("idx,box", [(1, (16, 16, 8)), (2, (16, 16, 8)), (5, (16, 16, 8))])
+def test_deterministic_current_is_bitwise_reproducible(P, idx, box):
+    cfg = workloads.config(idx, nx=box[0], ny=box[1], nz=box[2], deterministic_j=True)
+    nsp = len(cfg["species"])
+    _print("deterministic J", idx, box)
+    runs = []
+    for _ in range(2):
+        with P.Pic(cfg) as pic:
+            pic.step(6)
+            runs.append(_all_state(pic, nsp))
+    _assert_bitwise(runs[0], runs[1])
+    # the float-atomic flush agrees with it to rounding
+    cfg_f = workloads.reduced(idx, *box)
+    with P.Pic(cfg_f) as pic:
+        pic.step(6)
+        E, B, J, _ = _all_state(pic, nsp)
+    jmax = float(np.abs(runs[0][2]).max())
+    assert jmax > 0
+    # after 6 cycles the two histories differ by compounded FP32 rounding only
+    assert float(np.abs(J - runs[0][2]).max()) <= 1e-4 * jmax
+    assert float(np.abs(E - runs[0][0]).max()) <= 1e-4 * float(np.abs(E).max())
+
+
+@pytest.mark.parametrize("idx,box,warm", [(1, (16, 16, 8), 10), (2, (16, 16, 8), 10), (3, (16, 16, 8), 4)])
+def test_deterministic_current_one_step_parity(P, idx, box, warm):
+    cfg = workloads.config(idx, nx=box[0], ny=box[1], nz=box[2], deterministic_j=True)
+    _print("deterministic J parity", idx, box)
+    st = oracle.init_state(cfg)
+    oracle.step(st, warm)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+    _print(err)
+    assert err["jmax"] > 0
+    assert max(err["u"]) <= 1e-5
+    assert err["J"] <= 1e-4
+    assert err["E"] <= 1e-4 and err["B"] <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# checkpoint and resume
+
+def _checkpoint(pic, nsp):
+    E, B, J, parts = _all_state(pic, nsp)
+    return dict(E=E, B=B, J=J, parts=parts, run=pic.get_run_state())
+
+
+def _restore(pic, ck, run_state=True):
+    for s, p in enumerate(ck["parts"]):
+        pic.set_particles(s, p)
+    pic.set_fields(E=ck["E"], B=ck["B"], J=ck["J"])
+    if run_state:
+        pic.set_run_state(ck["run"])
+    pic.mark_reference()
+
+
+def test_resume_matches_uninterrupted_run_bitwise(P):
+    # electrons + C2+ ions with exact-rate ionisation between cycles; 32x16x16
+    # cells fire tens of events per call, keyed on the step counter
+    cfg = workloads.config(3, nx=32, ny=16, nz=16, deterministic_j=True)
+    nsp = len(cfg["species"])
+    events = []
+    with P.Pic(cfg) as a:                           # uninterrupted
+        a.step(2)
+        a.ionize("exact")
+        a.step(2)
+        events.append(a.ionize("exact")["ionized"])
+        a.step(2)
+        full = _all_state(a, nsp)
+        full_run = a.get_run_state()
+    with P.Pic(cfg) as b:                           # first half, checkpointed
+        b.step(2)
+        b.ionize("exact")
+        b.step(2)
+        ck = _checkpoint(b, nsp)
+    assert ck["run"]["step"] == 4
+    with P.Pic(cfg) as c:                           # resumed on a fresh handle
+        _restore(c, ck)
+        events.append(c.ionize("exact")["ionized"])
+        c.step(2)
+        resumed = _all_state(c, nsp)
+        assert c.get_run_state() == full_run
+    _print("events uninterrupted / resumed", events)
+    assert events[0] > 10 and events[0] == events[1]
+    _assert_bitwise(full, resumed)
+    # without the run state the draws restart at step 0: another history
+    with P.Pic(cfg) as d:
+        _restore(d, ck, run_state=False)
+        assert d.get_run_state()["step"] == 0
+        d.ionize("exact")
+        d.step(2)
+        other = _all_state(d, nsp)
+    assert not np.array_equal(other[3][1]["zstate"], full[3][1]["zstate"])
+
+
+def test_set_run_state_rejects_bad_values(P):
+    cfg = workloads.reduced(2, 16, 16, 8)
+    with P.Pic(cfg) as pic:
+        st = pic.get_run_state()
+        assert st["step"] == 0 and st["seed"] == cfg["grid"]["seed"]
+        assert st["weight_bound"][0] == pytest.approx(1.0 / 8)   # density 1, 8 ppc, dV 1
+        for bad in (dict(st, step=-1), dict(st, weight_bound=[0.5 * st["weight_bound"][0], st["weight_bound"][1]]),
+                    dict(st, weight_bound=[float("nan"), st["weight_bound"][1]])):
+            with pytest.raises(P.PicError) as e:
+                pic.set_run_state(bad)
+            assert e.value.code == -1
+        pic.set_run_state(dict(st, step=7, seed=123, weight_bound=[0.25, 0.25]))
+        got = pic.get_run_state()
+        assert got["step"] == 7 and got["seed"] == 123 and got["weight_bound"] == [0.25, 0.25]
+        pic.step(1)   # a coarser fixed-point scale still deposits within parity bounds
+        assert pic.get_run_state()["step"] == 8
+
+
+# ---------------------------------------------------------------------------
+# allocation failure
+
+class _FailingAllocator:
+    """torch device memory for the first `limit` requests, then NULL."""
+
+    def __init__(self, P, limit):
+        from paper_1606_02862_amd import _capi as A
+        self.limit, self.calls, self.live = limit, 0, {}
+        self._alloc = A.ALLOC_FN(self._do_alloc)
+        self._free = A.FREE_FN(self._do_free)
+        self.struct = A.AllocT(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, user):
+        self.calls += 1
+        if self.calls > self.limit:
+            return None
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _do_free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+def test_allocation_failure_returns_oom_and_frees_everything(P):
+    cfg = workloads.reduced(3, 16, 16, 8)   # fields, frames, arrival lists, ionisation buffers
+    full = _FailingAllocator(P, 1 << 30)
+    with P.Pic(cfg, allocator=full):
+        total = full.calls
+    assert total > 20 and not full.live
+    for limit in sorted({0, 1, 2, 3, 5, 8, 13, total // 2, total - 2, total - 1}):
+        a = _FailingAllocator(P, limit)
+        with pytest.raises(P.PicError) as e:
+            P.Pic(cfg, allocator=a)
+        assert e.value.code == -2, (limit, str(e.value))   # PIC_ERR_OOM
+        assert a.calls == limit + 1
+        assert not a.live, limit                            # every block handed back

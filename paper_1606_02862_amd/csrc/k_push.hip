@@ -263,33 +263,54 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
     const R* const pw = s.w + base;
     const uint8_t* const pzs = HAS_Z ? s.zs + base : nullptr;
 
-    // software pipeline: the next frame's particle is loaded while this one is computed
-    R nx0 = 0, ny0 = 0, nz0 = 0, nux = 0, nuy = 0, nuz = 0, nw = 0;
-    int nzs = 0;
-    if (tid < n) {
-        const unsigned u = RB * (unsigned)tid;
-        nx0 = at(px, u); ny0 = at(py, u); nz0 = at(pz, u);
-        nux = at(pux, u); nuy = at(puy, u); nuz = at(puz, u); nw = at(pw, u);
-        if constexpr (HAS_Z) nzs = pzs[tid];
-    }
-    for (int f = 0; f < n; f += NT) {
-        const int slot = f + tid;
-        if (slot >= n) break;
+    // ---- the frame loop: lane tid takes slot tid of every frame.  The
+    // particle streams are software-pipelined: the loads of a later frame are
+    // in flight while this one is computed.  With DEPTH2 (FP32 CIC) two
+    // register sets alternate and the loop is unrolled by two, so the loads of
+    // frame f + 2 are in flight during frame f and no register is copied
+    // before its load has returned; otherwise one set holds frame f + 1.
+    constexpr bool DEPTH2 = std::is_same<R, float>::value && ORDER == 1;
+    struct Part {
+        R x, y, z, ux, uy, uz, w;
+        int zs;
+    };
+    // unconditional (the last particle again past the end) so that no branch
+    // obscures the order of these loads relative to the stores before them
+    auto load_part = [&](int sl) {
+        const unsigned un = RB * (unsigned)sl;
+        Part p;
+        p.x = ld_part<STREAM>(px, un); p.y = ld_part<STREAM>(py, un); p.z = ld_part<STREAM>(pz, un);
+        p.ux = ld_part<STREAM>(pux, un); p.uy = ld_part<STREAM>(puy, un); p.uz = ld_part<STREAM>(puz, un);
+        p.w = ld_part<STREAM>(pw, un);
+        p.zs = 0;
+        if constexpr (HAS_Z) p.zs = pzs[sl];
+        return p;
+    };
+    // a copy of a prefetched set into new registers: an opaque move, so the
+    // register allocator cannot merge the copy with the set and the next loads
+    // of the set can target the set's own registers (no copy of an in-flight load)
+    auto fresh = [](const Part& a) {
+        Part c;
+        asm("v_mov_b32 %0, %1" : "=v"(c.x) : "v"(a.x));
+        asm("v_mov_b32 %0, %1" : "=v"(c.y) : "v"(a.y));
+        asm("v_mov_b32 %0, %1" : "=v"(c.z) : "v"(a.z));
+        asm("v_mov_b32 %0, %1" : "=v"(c.ux) : "v"(a.ux));
+        asm("v_mov_b32 %0, %1" : "=v"(c.uy) : "v"(a.uy));
+        asm("v_mov_b32 %0, %1" : "=v"(c.uz) : "v"(a.uz));
+        asm("v_mov_b32 %0, %1" : "=v"(c.w) : "v"(a.w));
+        asm("v_mov_b32 %0, %1" : "=v"(c.zs) : "v"(a.zs));
+        return c;
+    };
+    // valid = false: a lane past the end of the last frame of a pair runs the
+    // body on a copy of the last particle; it deposits and queues nothing, is
+    // never a leaver and only stores into its own free slot (slot < cap)
+    auto push_one = [&](const int slot, const Part& pp, const bool valid) {
         const unsigned u = RB * (unsigned)slot;  // byte offset of the slot
-        const R x0 = nx0, y0 = ny0, z0 = nz0;
-        const R ux0 = nux, uy0 = nuy, uz0 = nuz;
-        const R wgt = nw;
+        const R x0 = pp.x, y0 = pp.y, z0 = pp.z;
+        const R ux0 = pp.ux, uy0 = pp.uy, uz0 = pp.uz;
+        const R wgt = pp.w;
         R q = s.charge;
-        if constexpr (HAS_Z) q *= (R)nzs;
-        {   // unconditional (the last particle again past the end) so that no branch
-            // obscures the order of these loads relative to this iteration's stores
-            const int sn = slot + NT < n ? slot + NT : n - 1;
-            const unsigned un = RB * (unsigned)sn;
-            nx0 = ld_part<STREAM>(px, un); ny0 = ld_part<STREAM>(py, un); nz0 = ld_part<STREAM>(pz, un);
-            nux = ld_part<STREAM>(pux, un); nuy = ld_part<STREAM>(puy, un); nuz = ld_part<STREAM>(puz, un);
-            nw = ld_part<STREAM>(pw, un);
-            if constexpr (HAS_Z) nzs = pzs[sn];
-        }
+        if constexpr (HAS_Z) q *= (R)pp.zs;
 
         // ---- gather at node-centred and half-shifted positions per axis;
         // the Galerkin gather takes the shape one order lower (ORDER nodes)
@@ -349,10 +370,10 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         if constexpr (std::is_same<R, double>::value) {
             if (!ok) {
                 bad = true;
-                continue;
+                return;
             }
         }
-        bad |= !ok;
+        bad |= valid && !ok;
         if (!ok) { ux = ux0; uy = uy0; uz = uz0; }
         const R x1 = ok ? x0 + ddx : x0, y1 = ok ? y0 + ddy : y0, z1 = ok ? z0 + ddz : z0;
 
@@ -363,7 +384,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         const int fy1 = shape_weights<ORDER>(y1, w1y);
         const int fz1 = shape_weights<ORDER>(z1, w1z);
         const bool same = (fx1 == inx) && (fy1 == iny) && (fz1 == inz);
-        if (same) {
+        if (same && valid) {
             R DSx[T::NP], DSy[T::NP], DSz[T::NP];
 #pragma unroll
             for (int k = 0; k < T::NP; ++k) {
@@ -376,14 +397,14 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         }
         // queue the others; one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 s,
         // s the axis of a single-axis crossing in the per-wave queues, -1 for the others there
-        const unsigned long long qmask = __ballot(!same);
+        const unsigned long long qmask = __ballot(!same && valid);
         if (qmask) {
             if constexpr (WAVEQ) {  // the wave's own region, crossers of one axis first
                 const unsigned long long below = (1ull << lane) - 1ull;
                 const int nax = (fx1 != inx) + (fy1 != iny) + (fz1 != inz);
-                const unsigned long long smask = __ballot(nax == 1);
+                const unsigned long long smask = __ballot(valid && nax == 1);
                 const unsigned long long mmask = qmask & ~smask;
-                if (!same) {
+                if (!same && valid) {
                     const bool one = nax == 1;
                     const int slot = one ? wave * rw + qn + __popcll(smask & below)
                                          : wave * rw + rw - 1 - (qo + __popcll(mmask & below));
@@ -399,7 +420,7 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
                 int qb = 0;
                 if (lane == leader) qb = atomicAdd(&s_queue, __popcll(qmask));
                 qb = __shfl(qb, leader, 64);
-                if (!same) {
+                if (!same && valid) {
                     R4* e = g.qbuf + 2 * (qbase + qb + __popcll(qmask & ((1ull << lane) - 1ull)));
                     e[0] = make4(x0, y0, z0, qw);
                     e[1] = make4(x1, y1, z1, R(0));
@@ -412,8 +433,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         // over after the frame loop so no wave waits on a global atomic here
         st_part<STREAM>(px, u, x1); st_part<STREAM>(py, u, y1); st_part<STREAM>(pz, u, z1);
         st_part<STREAM>(pux, u, ux); st_part<STREAM>(puy, u, uy); st_part<STREAM>(puz, u, uz);
-        const bool left = (x1 < R(0)) || (x1 >= (R)SX) || (y1 < R(0)) || (y1 >= (R)SY) || (z1 < R(0)) ||
-                          (z1 >= (R)SZ);
+        const bool left = valid && ((x1 < R(0)) || (x1 >= (R)SX) || (y1 < R(0)) || (y1 >= (R)SY) ||
+                                    (z1 < R(0)) || (z1 >= (R)SZ));
         const unsigned long long lmask = __ballot(left);
         if (lmask) {
             const int leader = __ffsll((long long)lmask) - 1;
@@ -433,6 +454,53 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
                     at(pz, u) = rmin(rmax(z1, R(0)), zm);
                 }
             }
+        }
+    };
+    Part pa{}, pb{};
+    if (n > 0) {  // block-uniform; lanes past the end load the last particle again
+        pa = load_part(tid < n ? tid : n - 1);
+        if constexpr (DEPTH2) {
+            pb = load_part(NT + tid < n ? NT + tid : n - 1);
+            // set A has arrived, set B stays in flight: the loop's waits then
+            // count the steady state's loads and stores, not this prologue's
+            constexpr int LOADS = HAS_Z ? 8 : 7;
+            __builtin_amdgcn_s_waitcnt(0x0F70 | LOADS);  // vmcnt(LOADS)
+        }
+    }
+    if constexpr (DEPTH2) {
+        // pairs of frames whose second frame holds particles (so the first is
+        // full): every lane runs both halves, none leaves the loop early, and
+        // no memory access of the body lies on a path the compiler must treat
+        // as skippable, so the waits it places count the steady state.  The
+        // last frame of a pair ends at or below the slab's capacity (a
+        // multiple of the frame size above the count).
+        int f = 0;
+        for (; f + NT < n; f += 2 * NT) {
+            {
+                const int slot = f + tid;
+                const Part cur = fresh(pa);
+                pa = load_part(slot + 2 * NT < n ? slot + 2 * NT : n - 1);
+                push_one(slot, cur, true);
+            }
+            {
+                const int slot = f + NT + tid;
+                const Part cur = fresh(pb);
+                pb = load_part(slot + 2 * NT < n ? slot + 2 * NT : n - 1);
+                push_one(slot, cur, slot < n);
+            }
+        }
+        if (f < n) {  // a last, single frame (set A)
+            const int slot = f + tid;
+            if (slot < n) push_one(slot, fresh(pa), true);
+        }
+    } else {
+        (void)pb;
+        for (int f = 0; f < n; f += NT) {
+            const int slot = f + tid;
+            if (slot >= n) break;
+            const Part cur = pa;
+            pa = load_part(slot + NT < n ? slot + NT : n - 1);
+            push_one(slot, cur, true);
         }
     }
     if (bad) g.flags[FLAG_CFL] = 1;

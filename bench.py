@@ -34,7 +34,7 @@ import workloads  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "push_shear128_counters.json")
 PUSH_SOURCES = [os.path.join(ROOT, "paper_1606_02862_amd", "csrc", f)
-                for f in ("k_push.hip", "pic_migrate.hpp", "pic_device.hpp", "pic_internal.hpp")]
+                for f in ("k_push.hip", "pic_deposit.hpp", "pic_migrate.hpp", "pic_device.hpp", "pic_internal.hpp")]
 
 
 def algorithmic_bytes_per_push(n_particles: int, n_cells: int, order: int, es: int = 4) -> int:
@@ -88,9 +88,34 @@ def host_description():
     return cpu, os.cpu_count()
 
 
-def cpu_baseline(cfg_idx: int, box: int, steps: int, **grid) -> dict:
-    """The FP64 oracle (plain C, one thread) on a sub-box of the same workload
-    (grid: the same shape / gather overrides as the GPU run)."""
+def host_threads() -> int:
+    """Threads for the all-cores leg: OMP_NUM_THREADS when set (the GPU host
+    sets it to the CPU share of one GPU), else the CPUs this process may use."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def lscpu_summary() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+    except OSError:
+        return ""
+    keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)", "CPU max MHz")
+    return "; ".join(l.split(":", 1)[0].strip() + ": " + l.split(":", 1)[1].strip()
+                     for l in out.splitlines() if l.split(":", 1)[0].strip() in keep)
+
+
+def cpu_baseline(cfg_idx: int, box: int, steps: int, full: bool = True, full_steps: int = 3, **grid) -> dict:
+    """The FP64 oracle on the host: one thread on a sub-box of the same
+    workload (grid: the same shape / gather overrides as the GPU run), and,
+    with full, the oracle's cycle with its particle loop split over all host
+    threads (private current arrays) on the full-size workload, one warm-up
+    cycle and full_steps timed ones."""
     import oracle
     cfg = workloads.config(cfg_idx, nx=box, ny=box, nz=box, **grid)
     st = oracle.init_state(cfg)
@@ -98,11 +123,29 @@ def cpu_baseline(cfg_idx: int, box: int, steps: int, **grid) -> dict:
     t0 = time.perf_counter()
     oracle.step(st, steps)
     dt = time.perf_counter() - t0
+    del st
     cpu, ncpu = host_description()
-    return {"value": n * steps / dt, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{box}^3 periodic sub-box of the same workload ({n} particles), {steps} PIC cycles, "
-                      f"FP64 C oracle, single thread; host {cpu}, {ncpu} logical CPUs",
+    out = {"value": n * steps / dt, "unit": "particle updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{box}^3 periodic sub-box of the same workload ({n} particles), {steps} PIC cycles, "
+                     f"FP64 C oracle, single thread; host {cpu}, {ncpu} logical CPUs",
+           "seconds": dt, "host": {"cpu": cpu, "nproc": ncpu, "lscpu": lscpu_summary()}}
+    if full:
+        cfg = workloads.config(cfg_idx, **grid)
+        gc = cfg["grid"]
+        st = oracle.init_state(cfg)
+        n = sum(s.n for s in st.species if s.mobile)
+        nt = host_threads()
+        oracle.step_threads(st, 1, nt)
+        t0 = time.perf_counter()
+        used = oracle.step_threads(st, full_steps, nt)
+        dt = time.perf_counter() - t0
+        out["all_cores"] = {
+            "value": n * full_steps / dt, "unit": "particle updates/s", "cores": used,
+            "kind": "oracle cycle, particle loop split over threads (private current arrays)",
+            "sample": f"the full {gc['nx']}x{gc['ny']}x{gc['nz']} workload ({n} particles), 1 warm-up and "
+                      f"{full_steps} timed PIC cycles, FP64 C oracle on {used} threads",
             "seconds": dt}
+    return out
 
 
 def copy_calibration() -> int:
@@ -116,6 +159,27 @@ def copy_calibration() -> int:
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": 4 * n, "repeats": 3}), flush=True)
+    return 0
+
+
+def dword_calibration() -> int:
+    """A dword-per-lane copy of 1 GiB (the particle streams' access width,
+    from the probe library), three times: its FETCH_SIZE / WRITE_SIZE per GiB
+    give the counter scale for such streams."""
+    import ctypes
+    import torch
+    from paper_1606_02862_amd import build as B
+    lib = ctypes.CDLL(B.PROBE_LIB)
+    lib.probe_copy_dword.restype = ctypes.c_int
+    lib.probe_copy_dword.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    if lib.probe_copy_dword(src.data_ptr(), dst.data_ptr(), n, 3) != 0:
+        raise SystemExit("dword copy failed")
+    assert bool((dst == 1).all())
+    print(json.dumps({"dword_copy_bytes_each_way": 4 * n, "repeats": 3}), flush=True)
     return 0
 
 
@@ -256,6 +320,70 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     return out
 
 
+def lds_bytes_per_particle(order: int, galerkin: bool = False) -> tuple[int, int]:
+    """LDS bytes one particle moves in the particle kernel's in-line path:
+    the field gather reads (6 components, (order+1) nodes per axis, one order
+    lower along staggered axes with the Galerkin gather; 4 B each) and the
+    Esirkepov deposit of a particle that keeps its first shape node (per
+    current component (order+1)^2 lines of `order` nodes; 8-byte atomics)."""
+    p = order + 1
+    if galerkin:  # each component is staggered along one (E) or two (B) axes
+        reads = 3 * (order * p * p) + 3 * (order * order * p)
+    else:
+        reads = 6 * p ** 3
+    atomics = 3 * p * p * order
+    return 4 * reads, 8 * atomics
+
+
+def lds_peaks() -> dict:
+    """Measured LDS bandwidth of the device (bytes/s): conflict-free
+    ds_read_b64 and ds_add_u64 streams of the probe library."""
+    import ctypes
+    from paper_1606_02862_amd import build as B
+    lib = ctypes.CDLL(B.PROBE_LIB)
+    lib.probe_lds_bandwidth.restype = ctypes.c_double
+    lib.probe_lds_bandwidth.argtypes = [ctypes.c_int, ctypes.c_int]
+    return {"read": lib.probe_lds_bandwidth(0, 4000), "atomic": lib.probe_lds_bandwidth(1, 2000)}
+
+
+def shape_leg(P, torch, cfg_idx: int, steps: int, warmup: int, peaks: dict) -> dict:
+    """One workload's PIC cycle (the TSC workloads: 256x256x128 electrons and
+    protons, and the 128^3 Kelvin-Helmholtz shear flow): updates/s, the
+    particle kernel's time per launch, and its HBM and LDS rooflines."""
+    cfg = workloads.config(cfg_idx)
+    gc = cfg["grid"]
+    ncell = gc["nx"] * gc["ny"] * gc["nz"]
+    order = {"cic": 1, "tsc": 2, "pcs": 3}[gc["shape"]]
+    mobile = [s for s in cfg["species"] if s["mobile"]]
+    n = sum(ncell * s["ppc"] for s in mobile)
+    pic = P.Pic(cfg)
+    pic.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(pic.stream)
+    pic.step(steps)
+    t1.record(pic.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    pic.timing(1)
+    pic.step(steps)
+    tm = pic.timing(0)
+    pic.close()
+    push_s = tm["push_ms"] / steps * 1e-3            # all species' particle kernels of one cycle
+    hbm = sum(algorithmic_bytes_per_push(ncell * s["ppc"], ncell, order) for s in mobile)
+    rd, at = lds_bytes_per_particle(order, gc.get("gather", "standard") == "galerkin")
+    t_lds = n * rd / peaks["read"] + n * at / peaks["atomic"]
+    return {"workload": cfg["workload"], "particles": n, "steps": steps, "ms_per_step": ms,
+            "value": n / (ms * 1e-3), "unit": "particle updates/s",
+            "push_ms_per_step": push_s * 1e3, "push_launches_per_step": tm["push_launches"] / steps,
+            "roofline_hbm": {"achieved": hbm / push_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": hbm / push_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_step": hbm},
+            "roofline_lds": {"bytes_read_per_particle": rd, "bytes_atomic_per_particle": at,
+                             "peak_read": peaks["read"] / 1e9, "peak_atomic": peaks["atomic"] / 1e9, "unit": "GB/s",
+                             "t_min_ms": t_lds * 1e3, "frac": t_lds / push_s}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,18 +394,26 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-box", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--no-cpu-full", action="store_true",
+                    help="skip the all-cores oracle leg on the full-size workload")
     ap.add_argument("--no-ionize", action="store_true", help="skip the ionisation leg")
+    ap.add_argument("--no-tsc", action="store_true", help="skip the TSC workload lines (256x256x128 e+p, 128^3 KHI)")
+    ap.add_argument("--tsc-steps", type=int, default=10)
     ap.add_argument("--shape", choices=("cic", "tsc", "pcs"), help="override the workload's particle shape")
     ap.add_argument("--gather", choices=("standard", "galerkin"), help="override the field gather")
     ap.add_argument("--fp64", action="store_true",
                     help="the FP64 variant of the PIC cycle (the ionisation leg, FP32 only, is skipped)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--dword-calibration", action="store_true",
+                    help="only run a 1 GiB copy with one dword per lane per access (HBM counter calibration)")
     ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the counter summary behind roofline.traffic from four rocprofv3 --pmc runs")
     args = ap.parse_args(argv)
     if args.copy_calibration:
         return copy_calibration()
+    if args.dword_calibration:
+        return dword_calibration()
     if args.counter_summary:
         return counter_summary(*args.counter_summary)
 
@@ -367,11 +503,21 @@ def main(argv=None):
         "checks": {"gauss_max_over_rho_max": moments["gauss_max"] / max(moments["rho_max"], 1e-30),
                    "particles_after": sum(moments["count"])},
     }
+    peaks = lds_peaks()
+    rd, at = lds_bytes_per_particle(order, gc.get("gather", "standard") == "galerkin")
+    t_lds = n_particles * rd / peaks["read"] + n_particles * at / peaks["atomic"]
+    line["roofline"]["lds"] = {"bytes_read_per_particle": rd, "bytes_atomic_per_particle": at,
+                               "peak_read": peaks["read"] / 1e9, "peak_atomic": peaks["atomic"] / 1e9,
+                               "unit": "GB/s", "t_min_ms": t_lds * 1e3, "frac": t_lds / (push_avg_ms * 1e-3)}
+    if not args.no_tsc and not args.fp64 and args.config == 1 and not overridden:
+        line["tsc"] = {"ep256": shape_leg(P, torch, 2, args.tsc_steps, 3, peaks),
+                       "khi128": shape_leg(P, torch, 5, args.tsc_steps, 3, peaks)}
     if not args.no_ionize and not args.fp64:
         line["ionize"] = ionize_leg(P, torch, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         over = {k: getattr(args, k) for k in ("shape", "gather") if getattr(args, k)}
-        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps, **over)
+        line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_box, args.cpu_steps,
+                                            full=not args.no_cpu_full and not args.fp64, **over)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -30,7 +30,7 @@ def build(src: str = _SRC, out: str = _SO) -> str:
     src / out name another copy of the source and its library (the tests
     compile copies with planted mistakes to show that the pins catch them)."""
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-fopenmp",
                            "-shared", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
@@ -103,6 +103,8 @@ def _declare(L):
     L.orc_rho.argtypes = [gp, C.c_int, C.POINTER(_Particles), _D]
     L.orc_step.argtypes = [gp, C.c_int, C.POINTER(_Particles), _D, _D, _D, C.c_int, _D]
     L.orc_step.restype = C.c_int
+    L.orc_step_threads.argtypes = [gp, C.c_int, C.POINTER(_Particles), _D, _D, _D, C.c_int, C.c_int]
+    L.orc_step_threads.restype = C.c_int
     L.orc_init_species.argtypes = [gp, C.c_uint64, C.POINTER(_InitSpec), _D, _D, _D, _D, _D, _D, _D,
                                    C.POINTER(C.c_int64)]
 
@@ -303,6 +305,18 @@ def step(st: State, nsteps: int = 1, trace: bool = False):
     assert rc == 0
     st.step += nsteps
     return tr
+
+
+def step_threads(st: State, nsteps: int, nthreads: int) -> int:
+    """orc_step's cycle with the particle loop split over nthreads threads
+    (private current arrays summed in thread order); for timing the host's
+    cores.  Returns the number of threads that ran."""
+    structs = _structs(st.species)
+    used = lib().orc_step_threads(C.byref(st.grid), len(st.species), structs, _dp(st.E), _dp(st.B), _dp(st.J),
+                                  nsteps, nthreads)
+    assert used >= 1
+    st.step += nsteps
+    return used
 
 
 def rho(st: State):

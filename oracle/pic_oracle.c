@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t nx, ny, nz, order; /* order 1 = CIC, 2 = TSC, 3 = PCS */
@@ -406,12 +409,34 @@ void orc_rho(const orc_grid* g, int nsp, const orc_particles* sp, double* rho)
  *   -> B half step -> E full step with -J -> B half step.
  * Immobile species are skipped.  Positions are wrapped into [0, n_d).
  * trace (optional) receives per step: W_E^n, W_B^n, K^{n-1/2}, K^{n+1/2}. */
+/* Particle p of species S: gather, Boris, move, Esirkepov into J, wrap. */
+static void push_one(const orc_grid* g, orc_particles* S, int64_t p, const double* E, const double* B, double* J)
+{
+    const double len[3] = {(double)g->nx, (double)g->ny, (double)g->nz};
+    const double dl[3] = {g->dx, g->dy, g->dz};
+    double Ep[3], Bp[3];
+    orc_gather(g, E, B, 1, &S->x[p], &S->y[p], &S->z[p], Ep, Bp);
+    double q = charge_of(S, p);
+    double u[3] = {S->ux[p], S->uy[p], S->uz[p]};
+    boris1(q / S->m, g->dt, Ep, Bp, u);
+    S->ux[p] = u[0]; S->uy[p] = u[1]; S->uz[p] = u[2];
+    double gm = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double x0[3] = {S->x[p], S->y[p], S->z[p]}, x1[3];
+    for (int d = 0; d < 3; ++d) x1[d] = x0[d] + g->dt * u[d] / (gm * dl[d]);
+    esirkepov1(g, q * S->w[p], x0, x1, J);
+    for (int d = 0; d < 3; ++d) {
+        double v = fmod(x1[d], len[d]);
+        if (v < 0.0) v += len[d];
+        if (v >= len[d]) v -= len[d];
+        x1[d] = v;
+    }
+    S->x[p] = x1[0]; S->y[p] = x1[1]; S->z[p] = x1[2];
+}
+
 int orc_step(const orc_grid* g, int nsp, orc_particles* sp, double* E, double* B, double* J,
              int nsteps, double* trace)
 {
     const int64_t N = ncell(g);
-    const double len[3] = {(double)g->nx, (double)g->ny, (double)g->nz};
-    const double dl[3] = {g->dx, g->dy, g->dz};
     for (int st = 0; st < nsteps; ++st) {
         if (trace) {
             double wf[2];
@@ -426,25 +451,7 @@ int orc_step(const orc_grid* g, int nsp, orc_particles* sp, double* E, double* B
         for (int s = 0; s < nsp; ++s) {
             orc_particles* S = &sp[s];
             if (!S->mobile) continue;
-            for (int64_t p = 0; p < S->n; ++p) {
-                double Ep[3], Bp[3];
-                orc_gather(g, E, B, 1, &S->x[p], &S->y[p], &S->z[p], Ep, Bp);
-                double q = charge_of(S, p);
-                double u[3] = {S->ux[p], S->uy[p], S->uz[p]};
-                boris1(q / S->m, g->dt, Ep, Bp, u);
-                S->ux[p] = u[0]; S->uy[p] = u[1]; S->uz[p] = u[2];
-                double gm = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                double x0[3] = {S->x[p], S->y[p], S->z[p]}, x1[3];
-                for (int d = 0; d < 3; ++d) x1[d] = x0[d] + g->dt * u[d] / (gm * dl[d]);
-                esirkepov1(g, q * S->w[p], x0, x1, J);
-                for (int d = 0; d < 3; ++d) {
-                    double v = fmod(x1[d], len[d]);
-                    if (v < 0.0) v += len[d];
-                    if (v >= len[d]) v -= len[d];
-                    x1[d] = v;
-                }
-                S->x[p] = x1[0]; S->y[p] = x1[1]; S->z[p] = x1[2];
-            }
+            for (int64_t p = 0; p < S->n; ++p) push_one(g, S, p, E, B, J);
         }
         orc_update_b(g, 0.5 * g->dt, E, B);
         orc_update_e(g, g->dt, B, J, E);
@@ -515,4 +522,52 @@ void orc_init_species(const orc_grid* g, uint64_t seed, const orc_init_spec* sp,
                     id[p] = myid;
                 }
             }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The cycle of orc_step (no trace) with each species' particle loop split
+ * over nthreads threads (contiguous ranges), each depositing into a private
+ * current array; the private arrays are added into J in thread order after
+ * the loop.  For timing the CPU on all host cores only; orc_step is the
+ * reference.  Returns the number of threads that ran, or -1 if the private
+ * arrays cannot be allocated. */
+int orc_step_threads(const orc_grid* g, int nsp, orc_particles* sp, double* E, double* B, double* J,
+                     int nsteps, int nthreads)
+{
+    const int64_t N3 = 3 * ncell(g);
+    if (nthreads < 1) nthreads = 1;
+#ifndef _OPENMP
+    nthreads = 1;
+#endif
+    double* priv = (double*)malloc(sizeof(double) * (size_t)N3 * (size_t)nthreads);
+    if (!priv) return -1;
+    int used = 1;
+    for (int st = 0; st < nsteps; ++st) {
+        memset(priv, 0, sizeof(double) * (size_t)N3 * (size_t)nthreads);
+        for (int s = 0; s < nsp; ++s) {
+            orc_particles* S = &sp[s];
+            if (!S->mobile) continue;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthreads)
+#endif
+            {
+                int t = 0, nt = 1;
+#ifdef _OPENMP
+                t = omp_get_thread_num();
+                nt = omp_get_num_threads();
+#endif
+                if (t == 0) used = nt;
+                const int64_t lo = S->n * t / nt, hi = S->n * (t + 1) / nt;
+                for (int64_t p = lo; p < hi; ++p) push_one(g, S, p, E, B, priv + (size_t)t * N3);
+            }
+        }
+        memset(J, 0, sizeof(double) * N3);
+        for (int t = 0; t < used; ++t)
+            for (int64_t i = 0; i < N3; ++i) J[i] += priv[(size_t)t * N3 + i];
+        orc_update_b(g, 0.5 * g->dt, E, B);
+        orc_update_e(g, g->dt, B, J, E);
+        orc_update_b(g, 0.5 * g->dt, E, B);
+    }
+    free(priv);
+    return used;
 }

@@ -40,6 +40,24 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "probes.hip")
+PROBE_LIB = os.path.join(HERE, "libprobes.so")
+
+
+def build_probes(verbose: bool = False) -> str:
+    """The benchmark's measurement probes (LDS bandwidth, a dword copy for the
+    HBM counter calibration) as their own small library."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = ["hipcc", *CFLAGS, "-shared", "-o", tmp, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
@@ -52,6 +70,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_probes(verbose)
     return LIB
 
 

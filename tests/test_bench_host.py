@@ -52,3 +52,23 @@ def test_counter_summary_and_traffic(tmp_path, monkeypatch):
     d["k_push_sha256_16"] = "0" * 16                                   # the kernel changed since
     out.write_text(json.dumps(d))
     assert bench.traffic_from_profile(d["particles"]) is None
+
+
+def test_cpu_baseline_legs(monkeypatch):
+    # one thread on a sub-box, then the threaded oracle cycle on the full
+    # (here: the small 16^3) workload, with the host described
+    monkeypatch.setenv("OMP_NUM_THREADS", "2")
+    out = bench.cpu_baseline(0, 8, 2, full=True, full_steps=1)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0
+    assert out["host"]["nproc"] >= 1 and "CPU(s)" in out["host"]["lscpu"]
+    a = out["all_cores"]
+    assert a["cores"] == 2 and a["value"] > 0 and "16x16x16" in a["sample"]
+
+
+def test_lds_byte_model():
+    # gather reads (4 B) and in-line deposit atomics (8 B) per particle
+    assert bench.lds_bytes_per_particle(1) == (48 * 4, 12 * 8)      # CIC: 6 x 8 reads, 12 atomics
+    assert bench.lds_bytes_per_particle(2) == (162 * 4, 54 * 8)     # TSC: 6 x 27 reads, 54 atomics
+    assert bench.lds_bytes_per_particle(3) == (384 * 4, 144 * 8)    # PCS: 6 x 64 reads, 3 x 16 x 3 atomics
+    # Galerkin CIC: E_d reads 1 x 2 x 2 nodes, B_d 2 x 1 x 1
+    assert bench.lds_bytes_per_particle(1, galerkin=True)[0] == (3 * 4 + 3 * 2) * 4

@@ -544,3 +544,20 @@ def test_cycle_trace_bookkeeping_and_immobile():
     assert np.allclose(tr[1:, 2], tr[:-1, 3], rtol=0, atol=1e-14)
     we, wb = oracle.field_energy(st.grid, st.E, st.B)
     assert we > 0 and wb > 0
+
+
+def test_threaded_cycle_matches_serial_cycle():
+    """The all-cores CPU baseline (particle loop split over threads, private
+    current arrays summed after the loop) computes the cycle of orc_step: only
+    the order of the current sums differs, so states agree to rounding."""
+    cfg = workloads.config(1, nx=16, ny=16, nz=8)   # shear layer: many crossings
+    a = oracle.init_state(cfg)
+    b = a.copy()
+    oracle.step(a, 5)
+    used = oracle.step_threads(b, 5, 4)
+    assert used >= 1
+    for sa, sb in zip(a.species, b.species):
+        for k in ("x", "y", "z", "ux", "uy", "uz"):
+            assert np.max(np.abs(getattr(sa, k) - getattr(sb, k))) < 1e-12, k
+    for fa, fb in ((a.E, b.E), (a.B, b.B), (a.J, b.J)):
+        assert np.max(np.abs(fa - fb)) <= 1e-12 * max(np.abs(fa).max(), 1e-300)

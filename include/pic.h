@@ -375,6 +375,21 @@ int pic_cell_moments(pic_ctx* ctx, int species, double* ne_cm3, double* kT_ev);
 int pic_rate_eval(pic_ctx* ctx, pic_rate_mode_t mode, int species, int64_t n, const double* kT_ev,
                   const double* ne_cm3, const int32_t* Z, double* ln_rate);
 
+/* pic_rate_eval for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and results as pic_rate_eval; the n samples are staged
+ * through a static device buffer of the library (one per GPU, about 1.8 MB,
+ * held until the process ends, its address taken by pic_init) instead of
+ * memory from the handle's allocator, and nothing is allocated.
+ * n <= PIC_RATE_EVAL_NOALLOC_MAX, else PIC_ERR_ARG.  Every call on one GPU
+ * shares that buffer, so calls that overlap on one GPU (several threads or
+ * handles at once) race and must be serialised by the caller.  PIC_RATE_TABLE
+ * builds its table at the first use on the handle (a launch into memory taken
+ * at pic_init).  Synchronous. */
+#define PIC_RATE_EVAL_NOALLOC_MAX 65536
+int pic_rate_eval_noalloc(pic_ctx* ctx, pic_rate_mode_t mode, int species, int64_t n, const double* kT_ev,
+                          const double* ne_cm3, const int32_t* Z, double* ln_rate);
+
 /* The library's 64-point Gauss-Laguerre rule (weight e^{-x} on [0, inf)),
  * computed on the host at load time by the Golub-Welsch eigenvalue method
  * and refined by Newton steps on the Laguerre recurrence.  Needs no GPU. */

@@ -99,6 +99,7 @@ PIC_MLP_NPARAM = 4801
 PIC_MLP_SILU, PIC_MLP_RELU = 0, 1
 PIC_RATE_EXACT, PIC_RATE_MLP = 0, 1
 PIC_OPT_DETERMINISTIC_J, PIC_OPT_CONTINUITY = 1, 2
+PIC_RATE_EVAL_NOALLOC_MAX = 65536
 
 _DP = C.POINTER(C.c_double)
 _FP = C.POINTER(C.c_float)
@@ -127,6 +128,7 @@ SIGNATURES = {
     "pic_ionize": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IonizeStatsT)]),
     "pic_cell_moments": (C.c_int, [C.c_void_p, C.c_int, _DP, _DP]),
     "pic_rate_eval": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),
+    "pic_rate_eval_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),
     "pic_gauss_laguerre64": (C.c_int, [_DP, _DP]),
     "pic_mlp_train": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(MlpTrainCfgT), C.POINTER(MlpReportT)]),
     "pic_mlp_get_params": (C.c_int, [C.c_void_p, C.c_int, _FP, _DP, _DP, C.POINTER(C.c_int32)]),

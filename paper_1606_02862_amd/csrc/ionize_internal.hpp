@@ -115,6 +115,17 @@ hipError_t launch_mlp_init(uint64_t seed, float* P, float* m, float* v, hipStrea
 hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double* loss, hipStream_t st);
 hipError_t launch_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2, hipStream_t st);
 
+// Static staging of pic_rate_eval_noalloc (noalloc.hip): one device array per
+// GPU, its address taken once per device by noalloc_scratch_setup (with that
+// device current) and returned by noalloc_scratch (nullptr before).
+struct NoallocStaging {
+    double *kT, *ne, *out;
+    int32_t* Z;
+};
+hipError_t noalloc_scratch_setup(int device);
+unsigned char* noalloc_scratch(int device);
+NoallocStaging noalloc_staging(unsigned char* base);
+
 // ---------------------------------------------------------------- Lotz rate
 // One subshell (p, a, b, c, q) with E = p + kT x:
 //   <sigma v>_j = vbar (a q / (p kT)) e^{-p/kT} sum_k w_k ln(1 + x_k r) (1 - b e^{-c x_k r}),  r = kT / p,

@@ -31,6 +31,7 @@ struct pic_ctx {
     bool use_cb = false;
     std::vector<void*> owned;
     int32_t* flags_host = nullptr;  // pinned
+    int device = 0;                 // current device at pic_init
     int64_t step = 0;
     bool rho_prev_valid = false;    // diag.rho_prev holds rho before the last cycle (PIC_OPT_CONTINUITY)
     std::string err;
@@ -745,6 +746,10 @@ int pic_init(pic_ctx** out, const pic_grid_t* grid, const pic_species_t* species
         if (!msg.empty()) g_init_error = msg;
         return code;
     };
+    if (hipGetDevice(&c->device) != hipSuccess || noalloc_scratch_setup(c->device) != hipSuccess) {
+        c->err = "device query or static staging buffer address failed";
+        return bail(PIC_ERR_HIP);
+    }
     if (hipHostMalloc((void**)&c->flags_host, NFLAGS * sizeof(int32_t)) != hipSuccess) {
         c->flags_host = nullptr;
         c->err = "pinned host allocation failed";
@@ -1119,19 +1124,53 @@ int pic_cell_moments(pic_ctx* c, int s, double* ne_out, double* kT_out)
     return PIC_OK;
 }
 
-int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
-                  const int32_t* Z, double* ln_rate)
+}  // extern "C"
+
+namespace {
+
+// Arguments of pic_rate_eval(_noalloc); builds the rate table at its first use.
+int rate_eval_check(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
+                    const int32_t* Z, double* ln_rate)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP && mode != PIC_RATE_TABLE)
         return fail(c, PIC_ERR_ARG, "unknown rate mode %d", (int)mode);
     if (s < 0 || s >= c->nsp || c->sp[s].desc.z_max == 0) return fail(c, PIC_ERR_ARG, "species %d has no charge states", s);
     if (n < 0 || (n > 0 && (!kT || !ne || !Z || !ln_rate))) return fail(c, PIC_ERR_ARG, "bad sample arrays");
-    if (mode == PIC_RATE_TABLE) {
-        const int rc = ensure_rate_table(c, s);
-        if (rc != PIC_OK) return rc;
-    }
     if (mode == PIC_RATE_MLP && !c->mlp[s].ready) return fail(c, PIC_ERR_STATE, "species %d: no surrogate", s);
+    if (mode == PIC_RATE_TABLE) return ensure_rate_table(c, s);
+    return PIC_OK;
+}
+
+// ln nu of n host samples through device staging st (inputs copied in, the
+// rate kernel of the mode, the result copied out), synchronous.
+int rate_eval_staged(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
+                     const int32_t* Z, double* ln_rate, const NoallocStaging& st)
+{
+    hipError_t e = hipMemcpyAsync(st.kT, kT, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.ne, ne, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.Z, Z, n * 4, hipMemcpyHostToDevice, c->stream);
+    const IonTables tab = ion_tables(c, s);
+    if (e == hipSuccess)
+        e = mode == PIC_RATE_EXACT ? launch_ln_rate_exact(n, st.kT, st.ne, st.Z, tab, c->gl, st.out, c->stream)
+            : mode == PIC_RATE_TABLE
+                ? launch_ln_rate_table(n, st.kT, st.ne, st.Z, tab, c->rtab[s], c->gl, st.out, c->stream)
+                : launch_ln_rate_mlp(n, st.kT, st.ne, st.Z, tab, mlp_launch(c, s), c->gl, st.out, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ln_rate, st.out, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, PIC_ERR_HIP, "rate evaluation: %s", hipGetErrorString(e));
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
+                  const int32_t* Z, double* ln_rate)
+{
+    const int rc0 = rate_eval_check(c, mode, s, n, kT, ne, Z, ln_rate);
+    if (rc0 != PIC_OK) return rc0;
     if (n == 0) return PIC_OK;
     double* d = (double*)dev_alloc(c, (size_t)n * 3 * 8);
     int32_t* dz = (int32_t*)dev_alloc(c, (size_t)n * 4);
@@ -1140,22 +1179,24 @@ int pic_rate_eval(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const doub
         dev_free(c, dz);
         return fail(c, PIC_ERR_OOM, "rate evaluation buffers");
     }
-    int rc = PIC_OK;
-    hipError_t e = hipMemcpyAsync(d, kT, n * 8, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d + n, ne, n * 8, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(dz, Z, n * 4, hipMemcpyHostToDevice, c->stream);
-    const IonTables tab = ion_tables(c, s);
-    if (e == hipSuccess)
-        e = mode == PIC_RATE_EXACT ? launch_ln_rate_exact(n, d, d + n, dz, tab, c->gl, d + 2 * n, c->stream)
-            : mode == PIC_RATE_TABLE
-                ? launch_ln_rate_table(n, d, d + n, dz, tab, c->rtab[s], c->gl, d + 2 * n, c->stream)
-                : launch_ln_rate_mlp(n, d, d + n, dz, tab, mlp_launch(c, s), c->gl, d + 2 * n, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ln_rate, d + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) rc = fail(c, PIC_ERR_HIP, "rate evaluation: %s", hipGetErrorString(e));
+    const int rc = rate_eval_staged(c, mode, s, n, kT, ne, Z, ln_rate, NoallocStaging{d, d + n, d + 2 * n, dz});
     dev_free(c, d);
     dev_free(c, dz);
     return rc;
+}
+
+int pic_rate_eval_noalloc(pic_ctx* c, pic_rate_mode_t mode, int s, int64_t n, const double* kT, const double* ne,
+                          const int32_t* Z, double* ln_rate)
+{
+    const int rc = rate_eval_check(c, mode, s, n, kT, ne, Z, ln_rate);
+    if (rc != PIC_OK) return rc;
+    if (n > PIC_RATE_EVAL_NOALLOC_MAX)
+        return fail(c, PIC_ERR_ARG, "n = %lld exceeds PIC_RATE_EVAL_NOALLOC_MAX (%d)", (long long)n,
+                    PIC_RATE_EVAL_NOALLOC_MAX);
+    if (n == 0) return PIC_OK;
+    unsigned char* base = noalloc_scratch(c->device);
+    if (!base) return fail(c, PIC_ERR_STATE, "no static staging buffer on device %d", c->device);
+    return rate_eval_staged(c, mode, s, n, kT, ne, Z, ln_rate, noalloc_staging(base));
 }
 
 int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_report_t* out)

@@ -198,13 +198,16 @@ class Pic:
         A.check(self.lib.pic_cell_moments(self.h, species, _dptr(ne), _dptr(kT)), self.h)
         return ne, kT
 
-    def rate_eval(self, mode: str, species: int, kT, ne, Z) -> np.ndarray:
+    def rate_eval(self, mode: str, species: int, kT, ne, Z, noalloc: bool = False) -> np.ndarray:
+        """ln nu per sample; noalloc stages through the library's static buffer
+        (pic_rate_eval_noalloc, at most PIC_RATE_EVAL_NOALLOC_MAX samples)."""
         kT = np.ascontiguousarray(kT, dtype=np.float64)
         ne = np.ascontiguousarray(ne, dtype=np.float64)
         Z = np.ascontiguousarray(Z, dtype=np.int32)
         out = np.zeros(kT.size)
-        A.check(self.lib.pic_rate_eval(self.h, _MODE[mode], species, kT.size, _dptr(kT), _dptr(ne),
-                                       Z.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(out)), self.h)
+        fn = self.lib.pic_rate_eval_noalloc if noalloc else self.lib.pic_rate_eval
+        A.check(fn(self.h, _MODE[mode], species, kT.size, _dptr(kT), _dptr(ne),
+                   Z.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(out)), self.h)
         return out
 
     def mlp_train(self, species: int, n_train=1_000_000, batch=4096, steps=20000, lr=3e-3, lr_final=1e-5,

@@ -32,6 +32,10 @@ if ROOT not in sys.path:
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+RATE_COUNTERS = os.path.join(ROOT, "profiles", "rate_exact_fp64_counters.json")
+RATE_SOURCES = [os.path.join(ROOT, "paper_1606_02862_amd", "csrc", f)
+                for f in ("k_ionize.hip", "ionize_internal.hpp", "pic_device.hpp", "pic_internal.hpp")]
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "push_shear128_counters.json")
 PUSH_SOURCES = [os.path.join(ROOT, "paper_1606_02862_amd", "csrc", f)
                 for f in ("k_push.hip", "pic_deposit.hpp", "pic_migrate.hpp", "pic_device.hpp", "pic_internal.hpp")]
@@ -231,6 +235,62 @@ def counter_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_wr
     return 0
 
 
+def exact_rate_profile() -> int:
+    """One exact-quadrature ionisation step on the 128^3 electron-carbon
+    workload (2 PIC cycles first), for an FP64 counter pass over k_rate_exact."""
+    import torch  # noqa: F401
+    import paper_1606_02862_amd as P
+    P.load()
+    cfg = workloads.config(3)
+    gc = cfg["grid"]
+    with P.Pic(cfg) as pic:
+        pic.step(2)
+        r = pic.ionize("exact")
+    print(json.dumps({"ions_active": r["ions_active"], "rate_ms": r["rate_ms"],
+                      "ions": gc["nx"] * gc["ny"] * gc["nz"] * cfg["species"][1]["ppc"]}), flush=True)
+    return 0
+
+
+def exact_rate_fp64(rate_ms: float, ions: int):
+    """FP64 FLOP rate of k_rate_exact from the committed counter summary (FP64
+    FLOPs per dispatch over the same ion population), or None if it is absent
+    or the rate kernel's sources changed since."""
+    try:
+        with open(RATE_COUNTERS) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("sources_sha256_16") != source_hash(RATE_SOURCES) or d.get("ions") != ions:
+        return None
+    tflops = d["fp64_flops_per_dispatch"] / (rate_ms * 1e-3) / 1e12
+    return {"fp64_flops_per_ion": d["fp64_flops_per_dispatch"] / ions, "achieved_tflops": tflops,
+            "peak_tflops": FP64_PEAK_TFLOPS, "frac": tflops / FP64_PEAK_TFLOPS}
+
+
+def rate_counter_summary(run_dir: str, ions: int) -> int:
+    """Turn one rocprofv3 --pmc run of --exact-rate-profile (FP64 instruction
+    counters of k_rate_exact) into the summary behind ionize.exact_rate_fp64:
+    FP64 FLOPs per dispatch = 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave
+    instructions, stamped with the rate kernel's source hash."""
+    rows = [r for r in _counter_rows(run_dir) if "k_rate_exact" in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit(f"no k_rate_exact rows under {run_dir}")
+    c = {}
+    for r in rows:
+        c.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: sum(v) / len(v) for k, v in c.items()}
+    inst = {k: avg.get(f"SQ_INSTS_VALU_{k}_F64", 0.0) for k in ("ADD", "MUL", "FMA", "TRANS")}
+    flops = 64.0 * (inst["ADD"] + inst["MUL"] + inst["TRANS"] + 2.0 * inst["FMA"])
+    d = {"sources_sha256_16": source_hash(RATE_SOURCES), "ions": ions, "kernel": "k_rate_exact",
+         "fp64_wave_instructions": inst, "fp64_flops_per_dispatch": flops,
+         "counter_FLOPS_FP64": avg.get("SQ_INSTS_VALU_FLOPS_FP64"),
+         "counter_FLOPS_FP64_TRANS": avg.get("SQ_INSTS_VALU_FLOPS_FP64_TRANS"), "dispatches": len(c.get("SQ_INSTS_VALU_FMA_F64", []))}
+    with open(RATE_COUNTERS, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d), flush=True)
+    return 0
+
+
 def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     """Monte Carlo ionisation on the 128^3 electron-carbon workload: GPU time
     of the rate stage and of the whole step with the exact FP64 GL-64
@@ -275,6 +335,8 @@ def ionize_leg(P, torch, repeats: int = 3, cpu: bool = True) -> dict:
     out["rate_stage_speedup"] = out["exact"]["rate_ms"] / out["mlp"]["rate_ms"]
     # the whole pic_ionize (cell moments + rate + draw/append; moments and draw are the same in both modes)
     out["whole_step_speedup"] = out["exact"]["total_ms"] / out["mlp"]["total_ms"]
+    # how efficient the exact baseline is: its FP64 rate against the FP64 peak
+    out["exact_rate_fp64"] = exact_rate_fp64(out["exact"]["rate_ms"], out["ions"])
     out["rate_stage_ions_per_s"] = {m: out[m]["ions_active"] / (out[m]["rate_ms"] * 1e-3)
                                     for m in ("exact", "mlp", "table", "mlp_relu")}
     out["table_rate_stage_speedup"] = out["exact"]["rate_ms"] / out["table"]["rate_ms"]
@@ -405,8 +467,12 @@ def main(argv=None):
                     help="the FP64 variant of the PIC cycle (the ionisation leg, FP32 only, is skipped)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--exact-rate-profile", action="store_true",
+                    help="only one exact-quadrature ionisation step on the 128^3 carbon workload (FP64 counters)")
     ap.add_argument("--dword-calibration", action="store_true",
                     help="only run a 1 GiB copy with one dword per lane per access (HBM counter calibration)")
+    ap.add_argument("--rate-counter-summary", nargs=2, metavar=("RUN_DIR", "IONS"),
+                    help="write the FP64 counter summary of k_rate_exact from one rocprofv3 --pmc run")
     ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the counter summary behind roofline.traffic from four rocprofv3 --pmc runs")
     args = ap.parse_args(argv)
@@ -414,8 +480,12 @@ def main(argv=None):
         return copy_calibration()
     if args.dword_calibration:
         return dword_calibration()
+    if args.exact_rate_profile:
+        return exact_rate_profile()
     if args.counter_summary:
         return counter_summary(*args.counter_summary)
+    if args.rate_counter_summary:
+        return rate_counter_summary(args.rate_counter_summary[0], int(args.rate_counter_summary[1]))
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

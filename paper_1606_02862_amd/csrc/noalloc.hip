@@ -4,7 +4,7 @@
 //
 // The array's name is a host-side stand-in in host code; the device address
 // of each GPU's copy comes from hipGetSymbolAddress, taken once per device
-// (at pic_init, with that device current) and kept in noalloc_scratch[].
+// (at pic_init, with that device current) and kept per device.
 // Only that address is ever handed to kernels or copies.  Nothing in the
 // array needs to start at zero: a call copies its inputs in before the rate
 // kernel reads them, and the kernel writes every output that is copied back.

@@ -161,7 +161,7 @@ typedef struct {
     int32_t mobile;        /* 0: never pushed (still counted in rho) */
     int32_t coincident_with;
     int32_t z_init, z_max;
-    int32_t cap_ppc;       /* frame capacity in particles per cell (0: 3/2 ppc) */
+    int32_t cap_ppc;       /* frame capacity in particles per cell (0: 3/2 ppc; rounded up to even for TSC and PCS) */
     int32_t ionize_into;   /* species index of ionisation electrons, or -1 */
     double ionization_ev[PIC_MAX_ZSTATES];
     pic_lotz_shell_t lotz[PIC_MAX_ZSTATES][PIC_LOTZ_SHELLS];

@@ -265,11 +265,11 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
 
     // ---- the frame loop: lane tid takes slot tid of every frame.  The
     // particle streams are software-pipelined: the loads of a later frame are
-    // in flight while this one is computed.  With DEPTH2 (FP32 CIC) two
-    // register sets alternate and the loop is unrolled by two, so the loads of
+    // in flight while this one is computed.  With DEPTH2 (FP32 CIC and TSC)
+    // two register sets alternate and the loop is unrolled by two, so the loads of
     // frame f + 2 are in flight during frame f and no register is copied
     // before its load has returned; otherwise one set holds frame f + 1.
-    constexpr bool DEPTH2 = std::is_same<R, float>::value && ORDER == 1;
+    constexpr bool DEPTH2 = std::is_same<R, float>::value && ORDER <= 2;
     struct Part {
         R x, y, z, ux, uy, uz, w;
         int zs;
@@ -652,7 +652,9 @@ hipError_t launch_push(const GridViewT<R>& g, const SpeciesViewT<R>& s, int orde
 {
     // the deposit queue holds a full supercell, split evenly over the waves of a workgroup
     const int nt = order == 1 ? 256 : 512;
-    if ((s.cap + nt - 1) / nt * nt > g.qcap || g.qcap % (nt / 64) != 0) return hipErrorInvalidValue;
+    // whole frames per slab: the paired frame loop runs every lane of a pair's
+    // second frame, and a lane past the count stores into its own free slot
+    if (s.cap % nt != 0 || s.cap > g.qcap || g.qcap % (nt / 64) != 0) return hipErrorInvalidValue;
     if (s.cap_in > max_cap_in(order)) return hipErrorInvalidValue;
     R jscale = R(1), jinv = R(1);
     double jratio = 1.0;

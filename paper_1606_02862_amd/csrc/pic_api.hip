@@ -250,6 +250,7 @@ int alloc_species(pic_ctx* c, int s)
     const int nsc = c->g.nsc;
     int cap_ppc = d.cap_ppc > 0 ? d.cap_ppc : (d.ppc * 3 + 1) / 2;
     if (cap_ppc < 1) cap_ppc = 1;
+    if (c->order >= 2) cap_ppc += cap_ppc & 1;  // whole 512-particle frames per supercell
     v.cap = cap_ppc * SC_CELLS;
     int cap_in = v.cap / 4;
     cap_in = std::max(cap_in, 256);

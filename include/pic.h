@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 6
+#define PIC_ABI_VERSION 7
 #define PIC_MAX_SPECIES 4
 #define PIC_MAX_ZSTATES 8
 #define PIC_LOTZ_SHELLS 3
@@ -352,15 +352,25 @@ typedef struct {
     int64_t ionized;       /* ionisation events */
     int64_t fallback;      /* PIC_RATE_MLP / _TABLE: ions rated by the exact quadrature instead */
     int64_t electrons;     /* particles of the receiving species after the call */
-    double rate_ms;        /* GPU time of the rate stage (HIP events, handle's stream) */
+    double rate_ms;        /* GPU time of the rate stage (HIP events, handle's stream); -1 when fused */
     double total_ms;       /* GPU time of the whole call */
 } pic_ionize_stats_t;
 
 /* One ionisation step for every ionising species.  PIC_ERR_STATE if the
  * handle has no ionising species, or for PIC_RATE_MLP before a surrogate was
  * trained or loaded; PIC_ERR_CAPACITY if a supercell's electron frames are full
- * (an ion keeps only the events whose electrons found a slot). */
+ * (an ion keeps only the events whose electrons found a slot).
+ * With PIC_RATE_EXACT the moments, the rates and the draw run fused, one
+ * workgroup per supercell (rate_ms = -1); PIC_RATE_MLP and PIC_RATE_TABLE
+ * run staged as pic_ionize_staged.  Decisions and charge states are those
+ * of pic_ionize_staged; the order of the appended electrons within a
+ * supercell may differ (it is not defined by either). */
 int pic_ionize(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* out);
+
+/* The same step as three launches over the whole grid: cell moments, the
+ * rate of every ion, then the draw and append, with the rate stage timed on
+ * its own (rate_ms). */
+int pic_ionize_staged(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* out);
 
 /* Per-cell n_e (cm^-3) and kT_e (eV) of the electrons that species `species`
  * ionises into, as used by pic_ionize (computed now).  Host arrays of

@@ -78,6 +78,12 @@ hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const S
                               const DrawArgs& a, const double* nu, const DrawBuffers& b, unsigned long long* counters,
                               hipStream_t st);
 hipError_t launch_energy_loss(const GridView& g, const SpeciesView& el, const DrawBuffers& b, hipStream_t st);
+// The step with the exact rate fused (moments, rate, draw and append per
+// supercell in one kernel); ne, kT (and mom4) receive the cell moments as
+// the staged step's do.
+hipError_t launch_ionize_exact(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
+                               const DrawArgs& a, const DrawBuffers& db, double n_ref_over_dv, double* ne, double* kT,
+                               double* mom4, unsigned long long* counters, hipStream_t st);
 
 // ---------------------------------------------------------------- surrogate
 struct MlpLaunch {

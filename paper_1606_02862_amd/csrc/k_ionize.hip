@@ -2,7 +2,7 @@
 // exact Maxwellian-averaged Lotz rate by 64-point Gauss-Laguerre quadrature
 // in FP64, the Philox draw per ion and the append of the new electrons to
 // the ion's own supercell.
-#include "ionize_internal.hpp"
+#include "ionize_step.hpp"
 
 namespace pic {
 
@@ -14,45 +14,11 @@ namespace pic {
 __global__ __launch_bounds__(BLOCK) void k_moments(GridView g, SpeciesView e, double n_ref_over_dv, double* ne,
                                                    double* kT, double* mom4)
 {
-    __shared__ double acc[5][SC_CELLS];
+    __shared__ MomLds m;
     const int sc = blockIdx.x;
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) acc[k][tid] = 0.0;
-    __syncthreads();
-    const int n = e.count[sc];
-    const int64_t base = (int64_t)sc * e.cap;
-#pragma unroll 4
-    for (int t = tid; t < n; t += BLOCK) {
-        const int64_t p = base + t;
-        const int cell = (int)e.x[p] + SX * ((int)e.y[p] + SY * (int)e.z[p]);
-        const double w = e.w[p], ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
-        atomicAdd(&acc[0][cell], w);
-        atomicAdd(&acc[1][cell], w * ux);
-        atomicAdd(&acc[2][cell], w * uy);
-        atomicAdd(&acc[3][cell], w * uz);
-        atomicAdd(&acc[4][cell], w * (ux * ux + uy * uy + uz * uz));
-    }
-    __syncthreads();
-    const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
-    const int lx = tid & 7, ly = (tid >> 3) & 7, lz = tid >> 6;
-    const int64_t gi = (int64_t)(scx * SX + lx) + (int64_t)g.nx * ((scy * SY + ly) + (int64_t)g.ny * (scz * SZ + lz));
-    const double N = acc[0][tid];
-    double t_ev = 0.0, n_cm3 = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
-    if (N > 0.0) {
-        bx = acc[1][tid] / N, by = acc[2][tid] / N, bz = acc[3][tid] / N;
-        t_ev = ME_C2_EV * (acc[4][tid] / N - (bx * bx + by * by + bz * bz)) / 3.0;
-        t_ev = t_ev > 0.0 ? t_ev : 0.0;
-        n_cm3 = N * n_ref_over_dv;
-    }
-    ne[gi] = n_cm3;
-    kT[gi] = t_ev;
-    if (mom4) {
-        mom4[4 * gi] = N;
-        mom4[4 * gi + 1] = bx;
-        mom4[4 * gi + 2] = by;
-        mom4[4 * gi + 3] = bz;
-    }
+    moments_accumulate(e, sc, m);
+    const int cell = threadIdx.x;
+    moments_store(moments_cell(m, cell, n_ref_over_dv), cell_index(g, sc, cell), ne, kT, mom4);
 }
 
 hipError_t launch_moments(const GridView& g, const SpeciesView& e, double n_ref_over_dv, double* ne, double* kT,
@@ -118,38 +84,6 @@ hipError_t launch_ln_rate_exact(int64_t n, const double* kT, const double* ne, c
 }
 
 // ---------------------------------------------------------------- draw + append
-__device__ inline uint64_t word(const Philox4& r, int e)
-{
-    return e == 0 ? r.v[0] : e == 1 ? r.v[1] : e == 2 ? r.v[2] : r.v[3];
-}
-
-// Events of one ion.  One event: the Philox uniform u_0 of (id, species, 2,
-// step) below p = 1 - exp(-nu dt_phys).  Several: the waiting-time chain,
-// event e adding -ln(1 - u_e) / nu_{Z+e} while the running time stays below
-// dt_phys; u_e is word e % 4 of the block of (id, species, 2, step) for e < 4
-// and of (id, species, 6, step) after; later events take the exact rate.
-template <bool CHAIN>
-__device__ inline int ion_events(const IonTables& tab, const DrawArgs& a, uint32_t id, int Z0, double nu0, double kT,
-                                 double ne, const double* glx, const double* glw)
-{
-    const Philox4 r = philox4x64_10((uint64_t)id, (uint64_t)a.species_index, PURPOSE_IONIZE, (uint64_t)a.step, a.seed, 0);
-    if constexpr (!CHAIN) return u01(r.v[0]) < -expm1(-nu0 * a.dt_phys) ? 1 : 0;
-    Philox4 r2{};
-    double t = 0.0;
-    int nev = 0;
-    for (int e = 0; e < a.max_events && Z0 + e < tab.z_max; ++e) {
-        const double rate = e == 0 ? nu0 : rate_exact(kT, ne, tab, Z0 + e, glx, glw);
-        if (!(rate > 0.0)) break;
-        if (e == 4)
-            r2 = philox4x64_10((uint64_t)id, (uint64_t)a.species_index, PURPOSE_IONIZE_MORE, (uint64_t)a.step, a.seed, 0);
-        const double u = u01(e < 4 ? word(r, e) : word(r2, e - 4));
-        t += -log1p(-u) / rate;
-        if (!(t < a.dt_phys)) break;
-        ++nev;
-    }
-    return nev;
-}
-
 // Per ion with Z < z_max (counted, striped, at CNT_ACTIVE): its events, then
 // one electron per event at the end of the same supercell's electron frames
 // (one LDS atomic per ion with events), with the position, momentum and
@@ -163,17 +97,16 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
                                                        unsigned long long* counters)
 {
     __shared__ double glx[GL_NODES], glw[GL_NODES];
-    __shared__ int s_add, s_fired, s_active;
+    __shared__ DrawLds s_d;
     const int sc = blockIdx.x;
     const int tid = threadIdx.x;
     if (CHAIN && tid < GL_NODES) { glx[tid] = db.gl[tid]; glw[tid] = db.gl[GL_NODES + tid]; }
-    if (tid == 0) { s_add = 0; s_fired = 0; s_active = 0; }
+    if (tid == 0) s_d = DrawLds{0, 0, 0};
     __syncthreads();
     const int n = ion.count[sc];
     const int ebase = el.count[sc];
     const int room = el.cap - ebase;
     const int64_t base = (int64_t)sc * ion.cap;
-    const int64_t ebase64 = (int64_t)sc * el.cap;
     const int scx = sc % g.ncx, scy = (sc / g.ncx) % g.ncy, scz = sc / (g.ncx * g.ncy);
     bool full = false;
     int fired = 0, active = 0;
@@ -213,40 +146,14 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
             const int nev = ion_events<CHAIN>(tab, a, id, Z0, nus[k], CHAIN ? db.kT[gi] : 0.0,
                                               CHAIN ? db.ne[gi] : 0.0, glx, glw);
             if (nev == 0) continue;
-            const int b = atomicAdd(&s_add, nev);
-            int done = 0;
-            double dE = 0.0;
-            for (int e = 0; e < nev; ++e) {
-                const int kk = b + e;
-                if (kk >= room) { full = true; break; }
-                const int64_t q = ebase64 + ebase + kk;
-                const int znew = Z0 + e + 1;
-                el.x[q] = ion.x[p]; el.y[q] = ion.y[p]; el.z[q] = ion.z[p];
-                el.ux[q] = ion.ux[p]; el.uy[q] = ion.uy[p]; el.uz[q] = ion.uz[p];
-                el.w[q] = ion.w[p];
-                el.id[q] = (uint32_t)(a.id_base_new + (int64_t)(id - (uint32_t)a.ion_id_offset) * tab.z_max +
-                                      (znew - 1));
-                dE += tab.P[Z0 + e];
-                ++done;
-            }
-            if (done) {
-                ion.zs[p] = (uint8_t)(Z0 + done);
-                fired += done;
-                if (a.energy_loss) atomicAdd(&db.de[gi], (double)ion.w[p] * dE);
-            }
+            fired += append_events(ion, el, tab, a, db.de, sc, p, gi, id, Z0, nev, &s_d.add, ebase, room, full);
         }
     }
     if (full) g.flags[FLAG_CAPACITY] = 1;
-    if (fired) atomicAdd(&s_fired, fired);
-    if (active) atomicAdd(&s_active, active);
+    if (fired) atomicAdd(&s_d.fired, fired);
+    if (active) atomicAdd(&s_d.active, active);
     __syncthreads();
-    if (tid == 0) {
-        if (s_active) atomicAdd(&counters[CNT_ACTIVE + sc % CNT_STRIPES], (unsigned long long)s_active);
-        const int added = s_add < room ? s_add : room;
-        el.count[sc] = ebase + added;
-        if (a.energy_loss) db.old_count[sc] = ebase;
-        if (s_fired) atomicAdd(&counters[CNT_FIRED + sc % CNT_STRIPES], (unsigned long long)s_fired);
-    }
+    if (tid == 0) draw_finish(el, a, db, sc, ebase, room, s_d, counters);
 }
 
 hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
@@ -258,6 +165,73 @@ hipError_t launch_draw_append(const GridView& g, const SpeciesView& ion, const S
         hipLaunchKernelGGL(k_draw_append<true>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, nu, b, counters);
     else
         hipLaunchKernelGGL(k_draw_append<false>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, nu, b, counters);
+    return hipGetLastError();
+}
+
+// One ionisation step of one ion species with the exact rate, fused per
+// supercell (one workgroup each): the electron moments of its cells in LDS
+// (written to the grid as well), then for each of its ions the exact rate
+// from its cell's moments and the draw and append of its events.
+template <bool CHAIN>
+__global__ __launch_bounds__(BLOCK) void k_ionize_exact(GridView g, SpeciesView ion, SpeciesView el, IonTables tab,
+                                                        DrawArgs a, DrawBuffers db, double n_ref_over_dv, double* ne,
+                                                        double* kT, double* mom4, unsigned long long* counters)
+{
+    __shared__ MomLds mom;
+    __shared__ double glx[GL_NODES], glw[GL_NODES];
+    __shared__ DrawLds s_d;
+    const int sc = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < GL_NODES) { glx[tid] = db.gl[tid]; glw[tid] = db.gl[GL_NODES + tid]; }
+    if (tid == 0) s_d = DrawLds{0, 0, 0};
+    moments_accumulate(el, sc, mom);  // its barriers also publish the rule and the reset above
+    {
+        // each thread reads and rewrites only its own cell's column
+        const CellMoments cm = moments_cell(mom, tid, n_ref_over_dv);
+        moments_store(cm, cell_index(g, sc, tid), ne, kT, mom4);
+        mom.acc[0][tid] = cm.ne;
+        mom.acc[1][tid] = cm.kT;
+    }
+    __syncthreads();
+    const int n = ion.count[sc];
+    const int ebase = el.count[sc];
+    const int room = el.cap - ebase;
+    const int64_t base = (int64_t)sc * ion.cap;
+    bool full = false;
+    int fired = 0, active = 0;
+    for (int t = tid; t < n; t += BLOCK) {
+        const int64_t p = base + t;
+        const int Z = ion.zs[p];
+        if (Z >= tab.z_max) continue;
+        ++active;
+        const int cell = (int)ion.x[p] + SX * ((int)ion.y[p] + SY * (int)ion.z[p]);
+        const double cne = mom.acc[0][cell], ckT = mom.acc[1][cell];
+        const double nu0 = rate_exact(ckT, cne, tab, Z, glx, glw);
+        const uint32_t id = ion.id[p];
+        const int nev = ion_events<CHAIN>(tab, a, id, Z, nu0, ckT, cne, glx, glw);
+        if (nev) {
+            const int64_t gi = a.energy_loss ? cell_index(g, sc, cell) : 0;
+            fired += append_events(ion, el, tab, a, db.de, sc, p, gi, id, Z, nev, &s_d.add, ebase, room, full);
+        }
+    }
+    if (full) g.flags[FLAG_CAPACITY] = 1;
+    if (fired) atomicAdd(&s_d.fired, fired);
+    if (active) atomicAdd(&s_d.active, active);
+    __syncthreads();
+    if (tid == 0) draw_finish(el, a, db, sc, ebase, room, s_d, counters);
+}
+
+hipError_t launch_ionize_exact(const GridView& g, const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
+                               const DrawArgs& a, const DrawBuffers& db, double n_ref_over_dv, double* ne, double* kT,
+                               double* mom4, unsigned long long* counters, hipStream_t st)
+{
+    if (a.energy_loss && (!db.de || !db.old_count || !mom4)) return hipErrorInvalidValue;
+    if (a.max_events > 1)
+        hipLaunchKernelGGL(k_ionize_exact<true>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, db, n_ref_over_dv,
+                           ne, kT, mom4, counters);
+    else
+        hipLaunchKernelGGL(k_ionize_exact<false>, dim3(g.nsc), dim3(BLOCK), 0, st, g, ion, el, tab, a, db,
+                           n_ref_over_dv, ne, kT, mom4, counters);
     return hipGetLastError();
 }
 

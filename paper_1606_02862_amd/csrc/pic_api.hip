@@ -1028,7 +1028,18 @@ int pic_set_fields64(pic_ctx* c, const double* E, const double* B, const double*
     return c->fp64 ? set_fields_t<double>(c, E, B, J) : set_fields_t<float>(c, E, B, J);
 }
 
-int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
+}  // extern "C"
+
+namespace {
+
+// One ionisation step.  Staged: the cell moments, the rate of every ion and
+// the draw and append as three launches over the grid (the rate stage timed
+// on its own).  Fused (the exact rate): one launch that does all three per
+// supercell, so that the moments' streams of some workgroups overlap the
+// FP64 quadrature of others.  The surrogate and the table always run staged:
+// fused into the surrogate's persistent kernel (three waves per SIMD for its
+// registers) the moments and the draw measured slower than on their own.
+int ionize_impl(pic_ctx* c, pic_rate_mode_t mode, bool staged, pic_ionize_stats_t* out)
 {
     if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
     if (mode != PIC_RATE_EXACT && mode != PIC_RATE_MLP && mode != PIC_RATE_TABLE)
@@ -1060,19 +1071,7 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         HIPCHK(c, hipEventRecord(c->iev[0], c->stream));
         const pic_species_t& d = c->sp[s].desc;
         const bool eloss = d.energy_loss != 0;
-        HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, eloss ? c->mom4 : nullptr,
-                                 c->stream));
-        if (eloss) HIPCHK(c, launch_zero_f64(c->de, (int64_t)c->grid.nx * c->grid.ny * c->grid.nz, c->stream));
-        HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
-        if (mode == PIC_RATE_EXACT)
-            HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->stream));
-        else if (mode == PIC_RATE_TABLE)
-            HIPCHK(c, launch_rate_table(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->rtab[s], c->gl, c->counters,
-                                        c->fbl[s], c->stream));
-        else
-            HIPCHK(c, launch_rate_mlp(c->g, c->sp[s].v, tab, mlp_launch(c, s), c->ne, c->kT, c->nu[s], c->gl,
-                                      c->counters, c->fbl[s], c->stream));
-        HIPCHK(c, hipEventRecord(c->iev[2], c->stream));
+        const bool fused = !staged && mode == PIC_RATE_EXACT;
         DrawArgs a{};
         a.seed = c->grid.seed;
         a.step = c->step;
@@ -1084,14 +1083,32 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         a.energy_loss = eloss ? 1 : 0;
         const DrawBuffers db{c->ne, c->kT, c->gl, eloss ? c->mom4 : nullptr, eloss ? c->de : nullptr,
                              eloss ? c->old_count : nullptr};
-        HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], db, c->counters, c->stream));
+        const double nrdv = c->grid.n_ref_cm3 / dV;
+        if (eloss) HIPCHK(c, launch_zero_f64(c->de, (int64_t)c->grid.nx * c->grid.ny * c->grid.nz, c->stream));
+        if (fused) {
+            HIPCHK(c, launch_ionize_exact(c->g, c->sp[s].v, c->sp[e].v, tab, a, db, nrdv, c->ne, c->kT,
+                                          eloss ? c->mom4 : nullptr, c->counters, c->stream));
+        } else {
+            HIPCHK(c, launch_moments(c->g, c->sp[e].v, nrdv, c->ne, c->kT, eloss ? c->mom4 : nullptr, c->stream));
+            HIPCHK(c, hipEventRecord(c->iev[1], c->stream));
+            if (mode == PIC_RATE_EXACT)
+                HIPCHK(c, launch_rate_exact(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->gl, c->stream));
+            else if (mode == PIC_RATE_TABLE)
+                HIPCHK(c, launch_rate_table(c->g, c->sp[s].v, tab, c->ne, c->kT, c->nu[s], c->rtab[s], c->gl,
+                                            c->counters, c->fbl[s], c->stream));
+            else
+                HIPCHK(c, launch_rate_mlp(c->g, c->sp[s].v, tab, mlp_launch(c, s), c->ne, c->kT, c->nu[s], c->gl,
+                                          c->counters, c->fbl[s], c->stream));
+            HIPCHK(c, hipEventRecord(c->iev[2], c->stream));
+            HIPCHK(c, launch_draw_append(c->g, c->sp[s].v, c->sp[e].v, tab, a, c->nu[s], db, c->counters, c->stream));
+        }
         if (eloss) HIPCHK(c, launch_energy_loss(c->g, c->sp[e].v, db, c->stream));
         HIPCHK(c, hipEventRecord(c->iev[3], c->stream));
         unsigned long long cnt[CNT_WORDS];
         HIPCHK(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        float r = 0.f, t = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&r, c->iev[1], c->iev[2]));
+        float r = -1.f, t = 0.f;
+        if (!fused) HIPCHK(c, hipEventElapsedTime(&r, c->iev[1], c->iev[2]));
         HIPCHK(c, hipEventElapsedTime(&t, c->iev[0], c->iev[3]));
         rate_ms += r;
         total_ms += t;
@@ -1105,10 +1122,21 @@ int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
         c->sp[e].wmax = std::max(c->sp[e].wmax, c->sp[s].wmax);  // born electrons carry ion weights
         c->sp[e].wheld = std::max(c->sp[e].wheld, c->sp[s].wheld);
     }
-    st.rate_ms = rate_ms;
+    st.rate_ms = rate_ms < 0.0f ? -1.0 : rate_ms;
     st.total_ms = total_ms;
     if (out) *out = st;
     return read_flags(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_ionize(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out) { return ionize_impl(c, mode, false, out); }
+
+int pic_ionize_staged(pic_ctx* c, pic_rate_mode_t mode, pic_ionize_stats_t* out)
+{
+    return ionize_impl(c, mode, true, out);
 }
 
 int pic_cell_moments(pic_ctx* c, int s, double* ne_out, double* kT_out)

@@ -185,9 +185,12 @@ class Pic:
                     push_launches=t.push_launches, push_particles=t.push_particles)
 
     # ------------------------------------------------------------------ ionisation
-    def ionize(self, mode: str = "exact") -> dict:
+    def ionize(self, mode: str = "exact", staged: bool = False) -> dict:
+        """One ionisation step (pic_ionize, fused; staged: pic_ionize_staged,
+        with the rate stage timed on its own)."""
         st = A.IonizeStatsT()
-        A.check(self.lib.pic_ionize(self.h, _MODE[mode], C.byref(st)), self.h)
+        fn = self.lib.pic_ionize_staged if staged else self.lib.pic_ionize
+        A.check(fn(self.h, _MODE[mode], C.byref(st)), self.h)
         return dict(ions_active=st.ions_active, ionized=st.ionized, fallback=st.fallback, electrons=st.electrons,
                     rate_ms=st.rate_ms, total_ms=st.total_ms)
 

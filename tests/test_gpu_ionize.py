@@ -325,7 +325,9 @@ def test_ionize_mlp_with_every_ion_out_of_range_equals_exact(trained, P):
             parity.push_state(pic, s0)
             pic.mlp_set_params(1, params, ms, [1e5, 1e6, 1e19, 1e23], act)  # kT < 1e5 eV everywhere
             stats = pic.ionize(mode)
-            out[mode] = (stats, pic.get_particles(1), pic.get_particles(0))
+            el = pic.get_particles(0)
+            o = np.argsort(el["id"], kind="stable")  # appended electrons: their order is not defined
+            out[mode] = (stats, pic.get_particles(1), {k: v[o] for k, v in el.items()})
     se, ions_e, el_e = out["exact"]
     sm, ions_m, el_m = out["mlp"]
     _print("exact", se, "mlp", sm)

@@ -377,6 +377,16 @@ int pic_ionize_staged(pic_ctx* ctx, pic_rate_mode_t mode, pic_ionize_stats_t* ou
  * nx*ny*nz doubles, cell index i + nx (j + ny k); either may be NULL. */
 int pic_cell_moments(pic_ctx* ctx, int species, double* ne_cm3, double* kT_ev);
 
+/* The same moments left on the device: enqueues their computation on the
+ * handle's stream and returns the library's own arrays (nx*ny*nz doubles
+ * each, same cell index), without a copy or a synchronisation.  They stay
+ * owned by the library: the caller must not free or write them, and they
+ * are valid until the next pic_ionize, pic_ionize_staged or
+ * pic_cell_moments(_device) call on the handle (which overwrite them) or
+ * pic_destroy.  Reading them on another stream needs the caller's
+ * synchronisation with the handle's stream.  Either pointer may be NULL. */
+int pic_cell_moments_device(pic_ctx* ctx, int species, const double** ne_cm3, const double** kT_ev);
+
 /* ln nu (nu in 1/s) for n host samples (kT_e eV, n_e cm^-3, charge state Z of
  * species `species`), by the exact quadrature, the surrogate (with its exact
  * fallback outside the trained range) or the table (built at first use; exact

@@ -127,6 +127,7 @@ SIGNATURES = {
     "pic_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(TimingT)]),
     "pic_ionize": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IonizeStatsT)]),
     "pic_ionize_staged": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(IonizeStatsT)]),
+    "pic_cell_moments_device": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "pic_cell_moments": (C.c_int, [C.c_void_p, C.c_int, _DP, _DP]),
     "pic_rate_eval": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),
     "pic_rate_eval_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int64, _DP, _DP, _IP, _DP]),

@@ -1153,6 +1153,18 @@ int pic_cell_moments(pic_ctx* c, int s, double* ne_out, double* kT_out)
     return PIC_OK;
 }
 
+int pic_cell_moments_device(pic_ctx* c, int s, const double** ne_dev, const double** kT_dev)
+{
+    if (!c) return fail(nullptr, PIC_ERR_ARG, "ctx is NULL");
+    if (s < 0 || s >= c->nsp || !ionising(c, s)) return fail(c, PIC_ERR_ARG, "species %d does not ionise", s);
+    const int e = c->sp[s].desc.ionize_into;
+    const double dV = c->grid.dx * c->grid.dy * c->grid.dz;
+    HIPCHK(c, launch_moments(c->g, c->sp[e].v, c->grid.n_ref_cm3 / dV, c->ne, c->kT, nullptr, c->stream));
+    if (ne_dev) *ne_dev = c->ne;
+    if (kT_dev) *kT_dev = c->kT;
+    return PIC_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -201,6 +201,14 @@ class Pic:
         A.check(self.lib.pic_cell_moments(self.h, species, _dptr(ne), _dptr(kT)), self.h)
         return ne, kT
 
+    def cell_moments_device(self, species: int) -> tuple[int, int]:
+        """Device addresses of the library-owned per-cell n_e and kT_e arrays
+        (pic_cell_moments_device; nx*ny*nz doubles each, computed on the
+        handle's stream)."""
+        ne, kT = C.c_void_p(), C.c_void_p()
+        A.check(self.lib.pic_cell_moments_device(self.h, species, C.byref(ne), C.byref(kT)), self.h)
+        return ne.value, kT.value
+
     def rate_eval(self, mode: str, species: int, kT, ne, Z, noalloc: bool = False) -> np.ndarray:
         """ln nu per sample; noalloc stages through the library's static buffer
         (pic_rate_eval_noalloc, at most PIC_RATE_EVAL_NOALLOC_MAX samples)."""

@@ -71,6 +71,29 @@ def test_cell_moments_match_oracle(P):
     assert np.max(np.abs(kT - kT_ref) / kT_ref) < 1e-10
 
 
+def test_cell_moments_device_arrays_are_the_librarys(P):
+    """pic_cell_moments_device leaves n_e and kT_e in the library's own device
+    arrays: their contents equal the host copy, and the addresses stay the
+    same from call to call."""
+    import ctypes
+    cfg = _carbon_cfg()
+    with P.Pic(cfg) as pic:
+        pic.step(3)
+        ne_h, kT_h = pic.cell_moments(1)
+        pne, pkT = pic.cell_moments_device(1)
+        torch.cuda.synchronize()
+        # the HIP runtime already in the process (torch's), for a plain copy
+        hip = ctypes.CDLL(next(l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l))
+        ne_d, kT_d = np.empty(ne_h.size), np.empty(kT_h.size)
+        for dst, src in ((ne_d, pne), (kT_d, pkT)):
+            rc = hip.hipMemcpy(ctypes.c_void_p(dst.ctypes.data), ctypes.c_void_p(src), ctypes.c_size_t(dst.nbytes), 2)
+            assert rc == 0
+        assert pic.cell_moments_device(1) == (pne, pkT)
+    # recomputed: FP64 LDS sums, equal up to their order
+    assert np.allclose(ne_d, ne_h, rtol=1e-13, atol=0) and np.allclose(kT_d, kT_h, rtol=1e-12, atol=1e-12)
+    assert ne_h.max() > 0 and kT_h.max() > 0
+
+
 def _shared_carbon_state(pic, cfg, warm=4):
     st = oracle.init_state(cfg)
     oracle.step(st, warm)

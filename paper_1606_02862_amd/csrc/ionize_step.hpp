@@ -114,18 +114,50 @@ __device__ inline int ion_events(const IonTables& tab, const DrawArgs& a, uint32
     return nev;
 }
 
+// Stream compaction of the appends: every lane of the wave calls it with its
+// ion's event count (0 without events or without an ion).  The lanes' slots
+// follow from an exclusive prefix sum over the wave (a ballot and a bit count
+// when CHAIN is false and every count is 0 or 1), and the wave's block of
+// slots from one LDS atomic on *s_add (the supercell's appends so far).
+// Returns the lane's first slot index (relative to the supercell's electrons
+// before the step).
+template <bool CHAIN>
+__device__ inline int wave_reserve(int nev, int* s_add)
+{
+    const int lane = threadIdx.x & 63;
+    int incl, total;
+    if constexpr (CHAIN) {
+        incl = nev;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        total = __shfl(incl, 63, 64);
+    } else {
+        const unsigned long long m = __ballot(nev != 0);
+        incl = __popcll(m & (~0ull >> (63 - lane)));
+        total = __popcll(m);
+    }
+    int b = 0;
+    if (total) {  // wave-uniform
+        if (lane == 0) b = atomicAdd(s_add, total);
+        b = __shfl(b, 0, 64);
+    }
+    return b + incl - nev;
+}
+
 // The electrons of an ion's nev events, appended after the supercell's
-// electron frames: slots from one LDS atomic on *s_add (the supercell's
-// appends so far), at most `room` in all (the rest set `full`).  Each carries
-// the ion's position, momentum and weight and the id id_base_new + (ion id -
-// ion_id_offset) z_max + Z - 1 of the charge state Z it creates.  The ion's
-// charge state rises by the events that found a slot; with energy loss, w
-// times their ionisation energies goes to the cell's de.  Returns that count.
+// electron frames from slot index b (wave_reserve), at most `room` in all
+// (the rest set `full`).  Each carries the ion's position, momentum and
+// weight and the id id_base_new + (ion id - ion_id_offset) z_max + Z - 1 of
+// the charge state Z it creates.  The ion's charge state rises by the events
+// that found a slot; with energy loss, w times their ionisation energies goes
+// to the cell's de.  Returns that count.
 __device__ inline int append_events(const SpeciesView& ion, const SpeciesView& el, const IonTables& tab,
                                     const DrawArgs& a, double* de, int sc, int64_t p, int64_t gi, uint32_t id, int Z0,
-                                    int nev, int* s_add, int ebase, int room, bool& full)
+                                    int nev, int b, int ebase, int room, bool& full)
 {
-    const int b = atomicAdd(s_add, nev);
     int done = 0;
     double dE = 0.0;
     for (int e = 0; e < nev; ++e) {

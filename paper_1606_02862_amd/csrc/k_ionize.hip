@@ -133,20 +133,20 @@ __global__ __launch_bounds__(BLOCK) void k_draw_append(GridView g, SpeciesView i
 #pragma unroll
         for (int k = 0; k < DRAW_PER; ++k) {
             const int Z0 = zs[k];
-            if (Z0 >= tab.z_max) continue;
-            ++active;
             const int64_t p = base + c0 + k * BLOCK + tid;
-            // the ion's cell, for later events' rates and the energy account only
-            const bool need_cell = CHAIN || a.energy_loss;
-            const int64_t gi = need_cell ? (int64_t)(scx * SX + (int)ion.x[p]) +
-                                               (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) +
-                                                                (int64_t)g.ny * (scz * SZ + (int)ion.z[p]))
-                                         : 0;
-            const uint32_t id = ids[k];
-            const int nev = ion_events<CHAIN>(tab, a, id, Z0, nus[k], CHAIN ? db.kT[gi] : 0.0,
-                                              CHAIN ? db.ne[gi] : 0.0, glx, glw);
-            if (nev == 0) continue;
-            fired += append_events(ion, el, tab, a, db.de, sc, p, gi, id, Z0, nev, &s_d.add, ebase, room, full);
+            int nev = 0;
+            int64_t gi = 0;
+            if (Z0 < tab.z_max) {
+                ++active;
+                // the ion's cell, for later events' rates and the energy account only
+                if (CHAIN || a.energy_loss)
+                    gi = (int64_t)(scx * SX + (int)ion.x[p]) +
+                         (int64_t)g.nx * ((scy * SY + (int)ion.y[p]) + (int64_t)g.ny * (scz * SZ + (int)ion.z[p]));
+                nev = ion_events<CHAIN>(tab, a, ids[k], Z0, nus[k], CHAIN ? db.kT[gi] : 0.0, CHAIN ? db.ne[gi] : 0.0,
+                                        glx, glw);
+            }
+            const int b = wave_reserve<CHAIN>(nev, &s_d.add);  // every lane of the wave
+            if (nev) fired += append_events(ion, el, tab, a, db.de, sc, p, gi, ids[k], Z0, nev, b, ebase, room, full);
         }
     }
     if (full) g.flags[FLAG_CAPACITY] = 1;
@@ -199,19 +199,24 @@ __global__ __launch_bounds__(BLOCK) void k_ionize_exact(GridView g, SpeciesView 
     const int64_t base = (int64_t)sc * ion.cap;
     bool full = false;
     int fired = 0, active = 0;
-    for (int t = tid; t < n; t += BLOCK) {
+    for (int t0 = 0; t0 < n; t0 += BLOCK) {  // every lane runs every pass (the appends are per wave)
+        const int t = t0 + tid;
         const int64_t p = base + t;
-        const int Z = ion.zs[p];
-        if (Z >= tab.z_max) continue;
-        ++active;
-        const int cell = (int)ion.x[p] + SX * ((int)ion.y[p] + SY * (int)ion.z[p]);
-        const double cne = mom.acc[0][cell], ckT = mom.acc[1][cell];
-        const double nu0 = rate_exact(ckT, cne, tab, Z, glx, glw);
-        const uint32_t id = ion.id[p];
-        const int nev = ion_events<CHAIN>(tab, a, id, Z, nu0, ckT, cne, glx, glw);
+        const int Z = t < n ? (int)ion.zs[p] : tab.z_max;
+        int nev = 0, cell = 0;
+        uint32_t id = 0;
+        if (Z < tab.z_max) {
+            ++active;
+            cell = (int)ion.x[p] + SX * ((int)ion.y[p] + SY * (int)ion.z[p]);
+            const double cne = mom.acc[0][cell], ckT = mom.acc[1][cell];
+            const double nu0 = rate_exact(ckT, cne, tab, Z, glx, glw);
+            id = ion.id[p];
+            nev = ion_events<CHAIN>(tab, a, id, Z, nu0, ckT, cne, glx, glw);
+        }
+        const int b = wave_reserve<CHAIN>(nev, &s_d.add);
         if (nev) {
             const int64_t gi = a.energy_loss ? cell_index(g, sc, cell) : 0;
-            fired += append_events(ion, el, tab, a, db.de, sc, p, gi, id, Z, nev, &s_d.add, ebase, room, full);
+            fired += append_events(ion, el, tab, a, db.de, sc, p, gi, id, Z, nev, b, ebase, room, full);
         }
     }
     if (full) g.flags[FLAG_CAPACITY] = 1;

@@ -2,6 +2,7 @@
 
 `deposit_host.hip` drives the particle kernel's deposit arithmetic on the CPU;
 build() compiles it with hipcc (host code only runs; the device part is empty).
+`asan_plugin` points the CPU tests at AddressSanitizer builds of the host code.
 """
 from __future__ import annotations
 
@@ -16,15 +17,16 @@ SOURCES = [os.path.join(HERE, "deposit_host.hip")] + [
     os.path.join(CSRC, f) for f in ("pic_deposit.hpp", "pic_device.hpp", "pic_internal.hpp")]
 
 
-def build(force: bool = False) -> str:
-    """Compile libdeposit_host.so if it is missing or older than its sources."""
-    if not force and os.path.exists(SO):
-        t = os.path.getmtime(SO)
+def build(force: bool = False, so: str = SO, extra: tuple = ()) -> str:
+    """Compile libdeposit_host.so (or `so`, with the extra hipcc flags `extra`)
+    if it is missing or older than its sources."""
+    if not force and os.path.exists(so):
+        t = os.path.getmtime(so)
         if all(os.path.getmtime(s) <= t for s in SOURCES):
-            return SO
-    os.makedirs(BUILD, exist_ok=True)
-    tmp = SO + ".tmp"
-    subprocess.check_call(["hipcc", "-O2", "-std=c++17", "--offload-arch=gfx950", "-shared", "-fPIC",
+            return so
+    os.makedirs(os.path.dirname(so), exist_ok=True)
+    tmp = so + ".tmp"
+    subprocess.check_call(["hipcc", "-O2", "-std=c++17", "--offload-arch=gfx950", "-shared", "-fPIC", *extra,
                            "-o", tmp, SOURCES[0]], stderr=subprocess.DEVNULL)
-    os.replace(tmp, SO)
-    return SO
+    os.replace(tmp, so)
+    return so

@@ -19,9 +19,11 @@ struct MomLds {
 
 // Nearest-grid-point sums of the supercell's electrons, accumulated in FP64
 // by LDS atomics.  Every thread of the workgroup calls it; it starts and
-// ends with a barrier.
+// ends with a barrier.  The electrons are read once per step: non-temporal
+// loads keep them from displacing what the caches hold for the other stages.
 __device__ inline void moments_accumulate(const SpeciesView& e, int sc, MomLds& m)
 {
+    auto ld = [](const auto& a) { return __builtin_nontemporal_load(&a); };
     const int tid = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < 5; ++k) m.acc[k][tid] = 0.0;
@@ -31,8 +33,8 @@ __device__ inline void moments_accumulate(const SpeciesView& e, int sc, MomLds& 
 #pragma unroll 4
     for (int t = tid; t < n; t += BLOCK) {
         const int64_t p = base + t;
-        const int cell = (int)e.x[p] + SX * ((int)e.y[p] + SY * (int)e.z[p]);
-        const double w = e.w[p], ux = e.ux[p], uy = e.uy[p], uz = e.uz[p];
+        const int cell = (int)ld(e.x[p]) + SX * ((int)ld(e.y[p]) + SY * (int)ld(e.z[p]));
+        const double w = ld(e.w[p]), ux = ld(e.ux[p]), uy = ld(e.uy[p]), uz = ld(e.uz[p]);
         atomicAdd(&m.acc[0][cell], w);
         atomicAdd(&m.acc[1][cell], w * ux);
         atomicAdd(&m.acc[2][cell], w * uy);

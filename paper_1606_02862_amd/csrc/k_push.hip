@@ -558,6 +558,9 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         const int slot = s.holes[(int64_t)sc * s.cap_in + t];
         const int64_t p = base + slot;
         const R x1 = s.x[p], y1 = s.y[p], z1 = s.z[p];
+        const R lux = s.ux[p], luy = s.uy[p], luz = s.uz[p], lw = s.w[p];
+        const uint32_t lid = s.id[p];
+        const uint8_t lzs = HAS_Z ? s.zs[p] : (uint8_t)0;
         const int mvx = (x1 < R(0)) ? -1 : (x1 >= (R)SX ? 1 : 0);
         const int mvy = (y1 < R(0)) ? -1 : (y1 >= (R)SY ? 1 : 0);
         const int mvz = (z1 < R(0)) ? -1 : (z1 >= (R)SZ ? 1 : 0);
@@ -594,10 +597,10 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
             s.ix[q_] = rmin(x1 - (R)(mvx * SX), xm);
             s.iy[q_] = rmin(y1 - (R)(mvy * SY), ym);
             s.iz[q_] = rmin(z1 - (R)(mvz * SZ), zm);
-            s.iux[q_] = s.ux[p]; s.iuy[q_] = s.uy[p]; s.iuz[q_] = s.uz[p];
-            s.iw[q_] = s.w[p];
-            s.iid[q_] = s.id[p];
-            if constexpr (HAS_Z) s.izs[q_] = s.zs[p];
+            s.iux[q_] = lux; s.iuy[q_] = luy; s.iuz[q_] = luz;
+            s.iw[q_] = lw;
+            s.iid[q_] = lid;
+            if constexpr (HAS_Z) s.izs[q_] = lzs;
         } else {
             g.flags[FLAG_MIGRATE] = 1;
         }

@@ -9,9 +9,10 @@
 // With n particles, h holes and m arrivals the new count is n' = n - h + m.
 // Vacancies are the holes below n' plus the slots [n, n') when the supercell
 // grows; sources are the surviving particles at or above n' plus every
-// arrival.  The two lists have equal length and the k-th source moves into
-// the k-th vacancy; no source slot is also a destination, so the moves are
-// independent.
+// arrival.  The two lists have equal length and the k-th source (the
+// survivors, then arrival 0, 1, ...) moves into the k-th vacancy; no source
+// slot is also a destination, so the moves are independent.  Each thread
+// loads its first arrival while the holes are classified.
 #pragma once
 
 #include "pic_device.hpp"
@@ -46,6 +47,17 @@ __device__ inline int fill_supercell(const GridViewT<R>& g, const SpeciesViewT<R
         m -= np - s.cap;
         np = s.cap;
     }
+    // the first NT arrivals, loaded while the holes are classified
+    R pfx = R(0), pfy = R(0), pfz = R(0), pfux = R(0), pfuy = R(0), pfuz = R(0), pfw = R(0);
+    uint32_t pfid = 0;
+    uint8_t pfzs = 0;
+    if (tid < m) {
+        const int64_t q = inbox_index(s, g.nsc, par, sc, tid);
+        pfx = s.ix[q]; pfy = s.iy[q]; pfz = s.iz[q];
+        pfux = s.iux[q]; pfuy = s.iuy[q]; pfuz = s.iuz[q];
+        pfw = s.iw[q]; pfid = s.iid[q];
+        if (s.zs) pfzs = s.izs[q];
+    }
     const int lo = np < n ? np : n;  // survivors at or above n' must move down
     const int nmark = n - lo;        // <= h
 
@@ -67,7 +79,6 @@ __device__ inline int fill_supercell(const GridViewT<R>& g, const SpeciesViewT<R
     __syncthreads();
     const int ns_surv = counters[1];
     for (int t = n + tid; t < np; t += NT) s_vac[nv_holes + (t - n)] = t;
-    for (int t = tid; t < m; t += NT) s_src[ns_surv + t] = -1 - t;
     const int total = ns_surv + m;
     const int nvac = nv_holes + (np > n ? np - n : 0);
     if (tid == 0 && nvac != total) g.flags[FLAG_CAPACITY] = 1;  // cannot happen with consistent inputs
@@ -75,17 +86,24 @@ __device__ inline int fill_supercell(const GridViewT<R>& g, const SpeciesViewT<R
 
     const int64_t base = (int64_t)sc * s.cap;
     const int nmove = nvac < total ? nvac : total;
-    for (int t = tid; t < nmove; t += NT) {
+    const int nsv = ns_surv < nmove ? ns_surv : nmove;
+    for (int t = tid; t < nsv; t += NT) {  // survivors
         const int64_t d = base + s_vac[t];
-        const int src = s_src[t];
-        if (src >= 0) {
-            const int64_t q = base + src;
-            s.x[d] = s.x[q]; s.y[d] = s.y[q]; s.z[d] = s.z[q];
-            s.ux[d] = s.ux[q]; s.uy[d] = s.uy[q]; s.uz[d] = s.uz[q];
-            s.w[d] = s.w[q]; s.id[d] = s.id[q];
-            if (s.zs) s.zs[d] = s.zs[q];
+        const int64_t q = base + s_src[t];
+        s.x[d] = s.x[q]; s.y[d] = s.y[q]; s.z[d] = s.z[q];
+        s.ux[d] = s.ux[q]; s.uy[d] = s.uy[q]; s.uz[d] = s.uz[q];
+        s.w[d] = s.w[q]; s.id[d] = s.id[q];
+        if (s.zs) s.zs[d] = s.zs[q];
+    }
+    for (int a = tid; a < nmove - nsv; a += NT) {  // arrival a into vacancy nsv + a
+        const int64_t d = base + s_vac[nsv + a];
+        if (a == tid) {
+            s.x[d] = pfx; s.y[d] = pfy; s.z[d] = pfz;
+            s.ux[d] = pfux; s.uy[d] = pfuy; s.uz[d] = pfuz;
+            s.w[d] = pfw; s.id[d] = pfid;
+            if (s.zs) s.zs[d] = pfzs;
         } else {
-            const int64_t q = inbox_index(s, g.nsc, par, sc, -1 - src);
+            const int64_t q = inbox_index(s, g.nsc, par, sc, a);
             s.x[d] = s.ix[q]; s.y[d] = s.iy[q]; s.z[d] = s.iz[q];
             s.ux[d] = s.iux[q]; s.uy[d] = s.iuy[q]; s.uz[d] = s.iuz[q];
             s.w[d] = s.iw[q]; s.id[d] = s.iid[q];

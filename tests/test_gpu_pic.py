@@ -345,6 +345,44 @@ def test_one_step_parity_ragged_and_empty_supercells(P):
     assert err["u"][0] <= 1e-5 and err["J"] <= 1e-4 and err["x"][0] <= 2e-6
 
 
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_one_step_parity_leavers_in_every_direction(P, shape):
+    """Every particle of the centre supercell of a 3x3x3 grid of supercells
+    leaves it in one step: the directions cycle through all 26 neighbours
+    from one slot to the next (so each wave hands over to many destinations),
+    then a block of 300 leaves through the same face (one destination for
+    whole waves).  Positions after the step are global, so they check that
+    every leaver reached the right neighbour in the right place."""
+    cfg = workloads.config(1, nx=24, ny=24, nz=12, shape=shape)
+    g = oracle.grid_from_config(cfg)
+    r = workloads.rng(43)
+    dirs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]
+    d = np.array([dirs[i % 26] for i in range(26 * 20)] + [(1, 0, 0)] * 300)
+    n = len(d)
+    lo, ext = np.array([8.0, 8.0, 4.0]), np.array([8.0, 8.0, 4.0])
+    pos = np.empty((n, 3))
+    for a in range(3):
+        inside = lo[a] + r.uniform(0.5, ext[a] - 0.5, n)
+        pos[:, a] = np.where(d[:, a] < 0, lo[a] + 0.1, np.where(d[:, a] > 0, lo[a] + ext[a] - 0.1, inside))
+    u = 0.8 * d + r.normal(0, 0.01, (n, 3))
+    e = oracle.Species(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), u[:, 0].copy(), u[:, 1].copy(),
+                       u[:, 2].copy(), np.full(n, 1.0 / 16), np.arange(n, dtype=np.int64), q=-1.0, m=1.0)
+    E, B = workloads.random_fields(44, 24, 24, 12, amp=0.05)
+    st = oracle.State(g, [e], E, B, np.zeros_like(E), 0)
+    _print("leavers in every direction", shape, n)
+    with P.Pic(cfg) as pic:
+        s0 = parity.shared_start(pic, st)
+        err = parity.one_step_errors(pic, cfg, s0)
+        got = pic.get_particles(0)
+    _print(err)
+    assert np.array_equal(np.sort(got["id"]), np.arange(n))
+    # every particle left the centre supercell
+    c = np.stack([got["x"], got["y"], got["z"]], axis=1)
+    inside = np.all((c >= lo) & (c < lo + ext), axis=1)
+    assert not inside.any()
+    assert err["u"][0] <= 1e-5 and err["x"][0] <= 2e-6 and err["J"] <= 1e-4
+
+
 # ---------------------------------------------------------------------------
 # full-size workload in the benchmark's configuration: sampled parity
 

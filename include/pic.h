@@ -170,7 +170,8 @@ typedef struct {
 } pic_species_t;
 
 /* Device-memory provider.  alloc returns device memory of at least `bytes`
- * bytes aligned to 256 B (NULL on failure); free releases it. */
+ * bytes aligned to 256 B (NULL on failure; a pointer that is not so aligned
+ * is handed back to free and counts as a failure); free releases it. */
 typedef struct {
     void* (*alloc)(size_t bytes, void* user);
     void (*free)(void* ptr, void* user);

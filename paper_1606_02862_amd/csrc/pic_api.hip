@@ -98,6 +98,10 @@ void* dev_alloc(pic_ctx* c, size_t bytes)
     void* p = nullptr;
     if (c->use_cb) {
         p = c->alloc.alloc(bytes, c->alloc.user);
+        if (p && ((uintptr_t)p & 255)) {  // the kernels' vector accesses rely on the alignment
+            c->alloc.free(p, c->alloc.user);
+            p = nullptr;
+        }
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
         p = nullptr;
     }

@@ -251,3 +251,22 @@ def test_allocation_failure_returns_oom_and_frees_everything(P):
         assert e.value.code == -2, (limit, str(e.value))   # PIC_ERR_OOM
         assert a.calls == limit + 1
         assert not a.live, limit                            # every block handed back
+
+
+class _MisalignedAllocator(_FailingAllocator):
+    """torch device memory handed out 16 bytes past a 256-byte boundary."""
+
+    def _do_alloc(self, nbytes, user):
+        self.calls += 1
+        t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+        p = t.data_ptr() + 16
+        self.live[p] = t
+        return p
+
+
+def test_misaligned_allocation_counts_as_failure(P):
+    a = _MisalignedAllocator(P, 1 << 30)
+    with pytest.raises(P.PicError) as e:
+        P.Pic(workloads.reduced(0, 16, 16, 16), allocator=a)
+    assert e.value.code == -2     # PIC_ERR_OOM
+    assert a.calls >= 1 and not a.live

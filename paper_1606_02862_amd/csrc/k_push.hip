@@ -36,7 +36,7 @@
 // a per-supercell scratch list (wave ballot + popcount for the slots; for CIC
 // each wave owns a region of it, so no LDS counter is needed) and
 // deposited after the frame loop with the full (ORDER+2)-node window, so that
-// no wave runs the wide window for a few of its lanes.  For CIC and FP32 TSC
+// no wave runs the wide window for a few of its lanes.  For CIC and TSC
 // the queue keeps the particles whose first node changed along one axis only
 // apart from the others: they deposit on a window that is wide along that
 // axis alone (CIC 20 instead of 54 atomics, TSC 75 instead of 144).
@@ -202,9 +202,9 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
     // (no LDS atomic, and no wait on one, inside the frame loop); measured 1 %
     // faster for CIC and 2-3 % slower for TSC, which keeps the shared queue
     constexpr bool WAVEQ = std::is_same<R, float>::value && ORDER == 1;
-    // FP32 TSC: one queue per supercell, its single-axis crossers filled
-    // from the front and the others from the back (two LDS counters)
-    constexpr bool QCLASS = std::is_same<R, float>::value && ORDER == 2;
+    // the other CIC and TSC kernels: one queue per supercell, its single-axis
+    // crossers filled from the front and the others from the back (two LDS counters)
+    constexpr bool QCLASS = !WAVEQ && ORDER <= 2;
     constexpr int NW = NT / 64;
     __shared__ int s_qn[NW], s_qo[NW];
 
@@ -403,8 +403,8 @@ void k_push(GridViewT<R> g, SpeciesViewT<R> s, R jscale, R jinv, double jratio, 
         }
         // queue the others; one 32-byte record per particle: x0 y0 z0 qw | x1 y1 z1 s,
         // s the axis of a single-axis crossing where the queues keep that class
-        // apart (per-wave regions for CIC, front and back of the supercell's
-        // queue for TSC), -1 for the others there
+        // apart (per-wave regions for FP32 CIC, front and back of the supercell's
+        // queue for the other CIC and TSC kernels), -1 for the others there
         const unsigned long long qmask = __ballot(!same && valid);
         if (qmask) {
             if constexpr (WAVEQ) {  // the wave's own region, crossers of one axis first

@@ -118,8 +118,19 @@ hipError_t launch_mlp_gen(int64_t n, uint64_t seed, const MlpGen& a, const IonTa
                           double* r, hipStream_t st);
 hipError_t launch_mlp_standardize(int64_t n, const double* r, double* partial, double* mu_s, float* t, hipStream_t st);
 hipError_t launch_mlp_init(uint64_t seed, float* P, float* m, float* v, hipStream_t st);
-hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double* loss, hipStream_t st);
-hipError_t launch_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2, hipStream_t st);
+// A training step's gradient is summed without atomics: each workgroup of
+// the step kernel writes its sum (its waves in order) to its own row of a
+// partial buffer, MLP_PART_ROWS rows of MLP_PART_STRIDE floats (and its
+// squared-error sum to lpart), and the Adam kernel, or launch_mlp_grad, adds
+// the rows in row order.  *rows receives the number of rows written.
+constexpr int MLP_PART_ROWS = 64;
+constexpr int MLP_PART_STRIDE = (PIC_MLP_NPARAM + 63) / 64 * 64;
+hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* part, double* lpart, int* rows, hipStream_t st);
+// Adam on the master parameters with the summed gradient; *loss = the summed squared error
+hipError_t launch_mlp_adam(float* P, const float* part, int rows, const double* lpart, double* loss, float* m, float* v,
+                           float lr, float bc1, float bc2, hipStream_t st);
+// the summed gradient (PIC_MLP_NPARAM floats) and squared error
+hipError_t launch_mlp_grad(const float* part, int rows, const double* lpart, float* grad, double* loss, hipStream_t st);
 
 // Static staging of pic_rate_eval_noalloc (noalloc.hip): one device array per
 // GPU, its address taken once per device by noalloc_scratch_setup (with that

@@ -534,9 +534,13 @@ hipError_t launch_mlp_init(uint64_t seed, float* P, float* m, float* v, hipStrea
 
 // ---------------------------------------------------------------- training step
 // Forward + backward of a minibatch.  Sample slot b of the batch is training
-// sample idx[b] (explicit list) or, with idx == nullptr and draw_seed != 0,
-// Philox (b, step, 4, 0) mod n_data.  Every wave takes 16-sample tiles; grad
-// (NPARAM floats) and loss (sum of squared errors) accumulate atomically.
+// sample b (draw_seed == 0) or Philox (b, step, 4, 0) mod n_data.  Every wave
+// takes 16-sample tiles.  The block's gradient and squared-error sum (its
+// waves' partials added in wave order in LDS) go to row blockIdx.x of part
+// and lpart: no atomics, so the sums have a fixed order and training is
+// reproducible bit for bit.  (With one device-scope atomic add per wave and
+// parameter, those on one address queued behind each other beyond the L2 and
+// took a third of the step.)
 struct StepArgs {
     const float* X;      // [n_data][8]
     const float* t;      // [n_data]
@@ -547,13 +551,18 @@ struct StepArgs {
 };
 
 template <int ACT>
-__global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, float* grad, double* loss)
+__global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, float* part, double* lpart)
 {
     __shared__ float sW2[NH][NH + 1];                 // W2 (bf16-rounded), [out][in]
     __shared__ float sW1[NH][NIN], sB1[NH], sW3[NH];
-    __shared__ float h1t[BLOCK / 64][16][NH + 1];      // per-wave H1 tile [sample][k]
-    __shared__ float dz2t[BLOCK / 64][16][NH + 1];     // per-wave dZ2 tile [sample][n]
+    // per-wave H1 tiles [sample][k] and dZ2 tiles [sample][n]; after the
+    // rounds, the block's gradient
+    __shared__ float tiles[2][BLOCK / 64][16][NH + 1];
+    auto& h1t = tiles[0];
+    auto& dz2t = tiles[1];
+    static_assert(sizeof(tiles) >= NPARAM * sizeof(float), "the block gradient fits the tiles");
     __shared__ float gW1[BLOCK / 64][NH][NIN + 1];     // per-wave dW1 | db1
+    __shared__ double sL[BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
     for (int i = tid; i < NH * NH; i += BLOCK) sW2[i / NH][i % NH] = bf16r(P[OFF_W2 + i]);
@@ -683,68 +692,151 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_step(const float* P, StepArgs a, 
         }
         __syncthreads();  // the next round overwrites h1t / dz2t
     }
-    // ---- wave partials to the global accumulator
-    for (int tn = 0; tn < 4; ++tn)
-        for (int tk = 0; tk < 4; ++tk)
-            for (int r = 0; r < 4; ++r) {
-                // D[m = n][nn = k]: row 16tn + 4g + r, column 16tk + c
-                const int n = 16 * tn + 4 * g + r, k = 16 * tk + c;
-                unsafeAtomicAdd(&grad[OFF_W2 + n * NH + k], accW2[tn][tk][r]);
-            }
+    // ---- the block's gradient: every wave's partial of every parameter, added
+    // in wave order (the tiles are free after the last round's barrier)
+    float* sG = &tiles[0][0][0][0];
+    float w3[4], b2[4];
     for (int t = 0; t < 4; ++t) {
         float v = gW3[t], w = gB2[t];
         v += __shfl_xor(v, 16, 64); v += __shfl_xor(v, 32, 64);
         w += __shfl_xor(w, 16, 64); w += __shfl_xor(w, 32, 64);
-        if (g == 0) {
-            unsafeAtomicAdd(&grad[OFF_W3 + 16 * t + c], v);
-            unsafeAtomicAdd(&grad[OFF_B2 + 16 * t + c], w);
+        w3[t] = v;
+        b2[t] = w;
+    }
+    float b3s = gB3;
+    double l = lsum;
+    for (int o = 32; o > 0; o >>= 1) {
+        b3s += __shfl_xor(b3s, o, 64);
+        l += __shfl_xor(l, o, 64);
+    }
+    // what this lane owns: 64 entries of W2, 9 of W1 | b1, with g == 0 the
+    // lane's 4 + 4 of W3 and b2, and lane 0 b3
+    constexpr int N1 = NH * (NIN + 1) / 64;
+    static_assert(NH * (NIN + 1) % 64 == 0, "W1 | b1 split evenly over the lanes");
+    int pos[64 + N1 + 8];
+    float val[64 + N1 + 8];
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+        for (int tk = 0; tk < 4; ++tk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {  // D[m = n][nn = k]: row 16tn + 4g + r, column 16tk + c
+                pos[16 * tn + 4 * tk + r] = OFF_W2 + (16 * tn + 4 * g + r) * NH + 16 * tk + c;
+                val[16 * tn + 4 * tk + r] = accW2[tn][tk][r];
+            }
+#pragma unroll
+    for (int e = 0; e < N1; ++e) {
+        const int i = lane + 64 * e, k = i / (NIN + 1), q = i % (NIN + 1);
+        pos[64 + e] = q < NIN ? OFF_W1 + k * NIN + q : OFF_B1 + k;
+        val[64 + e] = gW1[wave][k][q];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        pos[64 + N1 + t] = OFF_W3 + 16 * t + c;
+        val[64 + N1 + t] = w3[t];
+        pos[64 + N1 + 4 + t] = OFF_B2 + 16 * t + c;
+        val[64 + N1 + 4 + t] = b2[t];
+    }
+    constexpr int NA = 64 + N1, NB = NA + 8;  // entries of every lane; of the g == 0 lanes
+    for (int w = 0; w < BLOCK / 64; ++w) {
+        if (wave == w) {
+            if (w > 0) {  // every load before the first store: one wait
+                float old[NB], old3 = 0.0f;
+#pragma unroll
+                for (int e = 0; e < NA; ++e) old[e] = sG[pos[e]];
+                if (g == 0)
+#pragma unroll
+                    for (int e = NA; e < NB; ++e) old[e] = sG[pos[e]];
+                if (lane == 0) old3 = sG[OFF_B3];
+#pragma unroll
+                for (int e = 0; e < NA; ++e) val[e] += old[e];
+                if (g == 0)
+#pragma unroll
+                    for (int e = NA; e < NB; ++e) val[e] += old[e];
+                b3s += old3;
+            }
+#pragma unroll
+            for (int e = 0; e < NA; ++e) sG[pos[e]] = val[e];
+            if (g == 0)
+#pragma unroll
+                for (int e = NA; e < NB; ++e) sG[pos[e]] = val[e];
+            if (lane == 0) {
+                sG[OFF_B3] = b3s;
+                sL[w] = l;
+            }
         }
+        __syncthreads();
     }
-    {
-        float v = gB3;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) unsafeAtomicAdd(&grad[OFF_B3], v);
-        double l = lsum;
-        for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
-        if (lane == 0) unsafeAtomicAdd(loss, l);
-    }
-    for (int i = lane; i < NH * (NIN + 1); i += 64) {
-        const int k = i / (NIN + 1), q = i % (NIN + 1);
-        const float v = gW1[wave][k][q];
-        if (q < NIN) unsafeAtomicAdd(&grad[OFF_W1 + k * NIN + q], v);
-        else unsafeAtomicAdd(&grad[OFF_B1 + k], v);
+    float* row = part + (size_t)blockIdx.x * MLP_PART_STRIDE;
+    for (int i = tid; i < NPARAM; i += BLOCK) row[i] = sG[i];
+    if (tid == 0) {
+        double ls = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) ls += sL[w];
+        lpart[blockIdx.x] = ls;
     }
 }
 
-hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* grad, double* loss, hipStream_t st)
+hipError_t launch_mlp_step(const float* P, const MlpStep& s, float* part, double* lpart, int* rows, hipStream_t st)
 {
     StepArgs a{s.X, s.t, s.n_data, s.batch, s.draw_seed, s.step};
     int blocks = s.batch / 16 / (BLOCK / 64);
-    if (blocks > 64) blocks = 64;
+    if (blocks > MLP_PART_ROWS) blocks = MLP_PART_ROWS;
     if (blocks < 1) blocks = 1;
-    if (s.act == PIC_MLP_RELU) hipLaunchKernelGGL(k_mlp_step<PIC_MLP_RELU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
-    else hipLaunchKernelGGL(k_mlp_step<PIC_MLP_SILU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, grad, loss);
+    *rows = blocks;
+    if (s.act == PIC_MLP_RELU) hipLaunchKernelGGL(k_mlp_step<PIC_MLP_RELU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, part, lpart);
+    else hipLaunchKernelGGL(k_mlp_step<PIC_MLP_SILU>, dim3(blocks), dim3(BLOCK), 0, st, P, a, part, lpart);
     return hipGetLastError();
 }
 
-// Adam on the FP32 master weights (beta1 0.9, beta2 0.999, eps 1e-8), then
-// clears the gradient accumulator.
-__global__ void k_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2)
+// The summed gradient of parameter i: four lanes per parameter each add every
+// fourth row in row order, then two shuffle steps add the four sums.  With
+// ADAM, Adam on the FP32 master weights (beta1 0.9, beta2 0.999, eps 1e-8);
+// otherwise the sum goes to grad.  Thread 0 also sums the rows' squared errors.
+template <bool ADAM>
+__global__ __launch_bounds__(BLOCK) void k_mlp_reduce(float* P, const float* part, int rows, const double* lpart,
+                                                      double* loss, float* grad, float* m, float* v, float lr, float bc1,
+                                                      float bc2)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NPARAM) return;
-    const float gi = grad[i];
-    const float mi = 0.9f * m[i] + 0.1f * gi;
-    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    P[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
-    grad[i] = 0.0f;
+    const int gid = blockIdx.x * BLOCK + threadIdx.x;
+    const int i = gid >> 2, j = gid & 3;
+    float sum = 0.0f;
+    if (i < NPARAM) {
+#pragma unroll 4
+        for (int r = j; r < rows; r += 4) sum += part[(size_t)r * MLP_PART_STRIDE + i];
+    }
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    if (gid == 0) {
+        double ls = 0.0;
+        for (int r = 0; r < rows; ++r) ls += lpart[r];
+        *loss = ls;
+    }
+    if (i >= NPARAM || j != 0) return;
+    if constexpr (ADAM) {
+        const float mi = 0.9f * m[i] + 0.1f * sum;
+        const float vi = 0.999f * v[i] + 0.001f * sum * sum;
+        m[i] = mi;
+        v[i] = vi;
+        P[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+    } else {
+        grad[i] = sum;
+    }
 }
 
-hipError_t launch_mlp_adam(float* P, float* grad, float* m, float* v, float lr, float bc1, float bc2, hipStream_t st)
+hipError_t launch_mlp_adam(float* P, const float* part, int rows, const double* lpart, double* loss, float* m, float* v,
+                           float lr, float bc1, float bc2, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, P, grad, m, v, lr, bc1, bc2);
+    if (rows < 1 || rows > MLP_PART_ROWS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_reduce<true>, dim3((4 * NPARAM + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, P, part, rows,
+                       lpart, loss, nullptr, m, v, lr, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float* part, int rows, const double* lpart, float* grad, double* loss, hipStream_t st)
+{
+    if (rows < 1 || rows > MLP_PART_ROWS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_reduce<false>, dim3((4 * NPARAM + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, nullptr, part,
+                       rows, lpart, loss, grad, nullptr, nullptr, 0.0f, 1.0f, 1.0f);
     return hipGetLastError();
 }
 

@@ -60,7 +60,9 @@ struct pic_ctx {
         float* params = nullptr;
         float* m = nullptr;
         float* v = nullptr;
-        float* grad = nullptr;
+        float* grad = nullptr;   // a summed gradient (pic_mlp_loss_grad)
+        float* part = nullptr;   // a training step's per-workgroup gradient rows
+        double* lpart = nullptr; // and squared-error sums
         double mu = 0.0, s = 1.0;
         double t_min = 1.0, t_max = 1e4, n_min = 1e19, n_max = 1e23;
         int act = PIC_MLP_SILU;
@@ -312,7 +314,9 @@ int alloc_ionisation(pic_ctx* c)
             return fail(c, PIC_ERR_OOM, "device allocation of ionisation rates failed");
         pic_ctx::Mlp& m = c->mlp[s];
         if (!(m.params = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.m = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) ||
-            !(m.v = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.grad = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)))
+            !(m.v = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) || !(m.grad = (float*)dev_alloc(c, PIC_MLP_NPARAM * 4)) ||
+            !(m.part = (float*)dev_alloc(c, (size_t)MLP_PART_ROWS * MLP_PART_STRIDE * 4)) ||
+            !(m.lpart = (double*)dev_alloc(c, (size_t)MLP_PART_ROWS * 8)))
             return fail(c, PIC_ERR_OOM, "device allocation of the surrogate failed");
         HIPCHK(c, launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream));
         if (c->sp[s].desc.energy_loss && !c->de) {
@@ -1277,19 +1281,20 @@ int pic_mlp_train(pic_ctx* c, int s, const pic_mlp_train_cfg_t* cfg, pic_mlp_rep
     if (e == hipSuccess) e = launch_mlp_gen(n, cfg->seed, ga, tab, c->gl, X, r, c->stream);
     if (e == hipSuccess) e = launch_mlp_standardize(n, r, scratch, mu_s, t, c->stream);
     if (e == hipSuccess) e = launch_mlp_init(cfg->seed, m.params, m.m, m.v, c->stream);
-    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
     if (e == hipSuccess) e = launch_zero_f64(losses, cfg->steps, c->stream);
     const uint64_t draw_seed = (cfg->seed ^ 0x5DEECE66DULL) | 1ULL;
     double b1t = 1.0, b2t = 1.0;
     for (int it = 0; it < cfg->steps && e == hipSuccess; ++it) {
         MlpStep ms{X, t, n, cfg->batch, draw_seed, it, cfg->activation};
-        e = launch_mlp_step(m.params, ms, m.grad, losses + it, c->stream);
+        int rows = 0;
+        e = launch_mlp_step(m.params, ms, m.part, m.lpart, &rows, c->stream);
         b1t *= 0.9;
         b2t *= 0.999;
         const double lr = cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) *
                                               (1.0 + std::cos(3.14159265358979323846 * it / cfg->steps));
         if (e == hipSuccess)
-            e = launch_mlp_adam(m.params, m.grad, m.m, m.v, (float)lr, (float)(1.0 - b1t), (float)(1.0 - b2t), c->stream);
+            e = launch_mlp_adam(m.params, m.part, rows, m.lpart, losses + it, m.m, m.v, (float)lr, (float)(1.0 - b1t),
+                                (float)(1.0 - b2t), c->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(c->iev[1], c->stream);
     std::vector<double> lh(cfg->steps);
@@ -1377,14 +1382,13 @@ int pic_mlp_loss_grad(pic_ctx* c, int s, int64_t n, const float* X, const float*
     }
     hipError_t e = hipMemcpyAsync(dX, X, n * 8 * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dX + n * 8, t, n * 4, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
-    if (e == hipSuccess) e = launch_zero_f64(dl, 1, c->stream);
     MlpStep ms{dX, dX + n * 8, n, (int)n, 0, 0, m.act};
-    if (e == hipSuccess) e = launch_mlp_step(m.params, ms, m.grad, dl, c->stream);
+    int rows = 0;
+    if (e == hipSuccess) e = launch_mlp_step(m.params, ms, m.part, m.lpart, &rows, c->stream);
+    if (e == hipSuccess) e = launch_mlp_grad(m.part, rows, m.lpart, m.grad, dl, c->stream);
     double lsum = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(grad, m.grad, PIC_MLP_NPARAM * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&lsum, dl, 8, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = launch_zero_f32(m.grad, PIC_MLP_NPARAM, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dev_free(c, dX);
     dev_free(c, dl);

@@ -209,6 +209,28 @@ def test_mlp_gradient_matches_oracle_backprop(P, act):
         assert rel < 2e-2 and cos > 0.999, k
 
 
+def test_mlp_training_is_bitwise_reproducible(P):
+    """The training step sums its gradient without atomics (per-workgroup rows
+    added in a fixed order), so two trainings from one seed give the same
+    parameters bit for bit, and the gradient entry point the same gradient."""
+    cfg = _carbon_cfg((8, 8, 4))
+    out = []
+    for _ in range(2):
+        with P.Pic(cfg) as pic:
+            rep = pic.mlp_train(1, seed=7, n_train=65536, batch=4096, steps=300)
+            p = pic.mlp_get_params(1)
+            T, ne, Z = workloads.loguniform_rate_inputs(14, 1024)
+            X = mlp.features(T, ne, Z)
+            g = pic.mlp_loss_grad(1, X, workloads.rng(15).normal(size=1024))
+        out.append((rep, p, g))
+    (r0, p0, g0), (r1, p1, g1) = out
+    assert r0["loss_first"] == r1["loss_first"] and r0["loss_last"] == r1["loss_last"]
+    assert r0["loss_last"] < r0["loss_first"]
+    assert np.array_equal(p0[0].view(np.uint32), p1[0].view(np.uint32))
+    assert np.array_equal(p0[1], p1[1])
+    assert g0[0] == g1[0] and np.array_equal(g0[1].view(np.uint32), g1[1].view(np.uint32))
+
+
 @pytest.mark.parametrize("act", ["silu", "relu"])
 def test_mlp_inference_matches_oracle_forward(P, act):
     """The fused inference kernel (transposed MFMA layout, augmented layer-1 K,
